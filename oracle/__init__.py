@@ -1,0 +1,30 @@
+"""Double-precision CPU oracle for the radiation-reaction PIC hot path.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product library imports, links or
+runs this package; only the test suite, the smoke check and the benchmark's
+CPU-baseline leg use it.  It shares no code with the GPU path: the two meet
+only through the seeded inputs of the ``workloads`` package.
+
+Contents and what they follow (Tamburini et al., "Radiation Reaction Effects
+on Radiation Pressure Acceleration"):
+
+* ``pusher``   - Boris push for the Lorentz force and the RR force of
+                 Eq. (f_r), combined by the leapfrog splitting of
+                 Eqs. (tot)-(estimgamma), Section 3; friction coefficient d of
+                 Eq. (damping) and the lab-frame LL force of Eq. (3dLL).
+* ``analytic`` - exact plane-wave orbits without RR and with the
+                 non-derivative LL force (Section 2 and the single-electron
+                 test of Section 3), uniform-field gyration and radiative
+                 cooling closed forms.
+* ``contract`` - the integer (fixed-point) current-deposition contract,
+                 evaluated in float32 exactly as the GPU stores its state.
+* ``pic``      - a plain 1D3V PIC loop (laser-foil problem of Section 4)
+                 with Yee fields, linear weighting and charge-conserving
+                 current deposition.
+* ``rng``      - SplitMix64 counter-based generator for the quiet start.
+* ``spectrum`` - ion energy spectrum, its peak and its full width at half
+                 maximum.
+
+Parity status per function is stated in each module header.
+"""
+from . import pusher, analytic, contract, pic, rng, spectrum  # noqa: F401

@@ -1,0 +1,56 @@
+"""Ion energy spectrum and its peak and width (Section 4 spectra, f(E) =
+protons per unit energy).
+
+TEST INFRASTRUCTURE ONLY (see package header).
+
+Reading: kinetic energy per proton E = (gamma - 1) M m_e c^2 with
+m_e c^2 = 0.51099895 MeV; weighted histogram on [0, e_max]; the peak is the
+mode refined by a parabola through the three bins around it; the width is
+the full width at half maximum, found by linear interpolation on both
+flanks.  Pins: exact peak and width of sampled Gaussians (tests).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+MEC2_MEV = 0.51099895
+
+
+def ion_energies_mev(u, mass_ratio):
+    u = np.asarray(u, dtype=np.float64).reshape(-1, 3)
+    return (np.sqrt(1.0 + np.sum(u * u, axis=1)) - 1.0) * mass_ratio * MEC2_MEV
+
+
+def histogram(E, w, bins, e_max):
+    h, edges = np.histogram(E, bins=bins, range=(0.0, e_max), weights=w)
+    return h / (edges[1] - edges[0]), edges
+
+
+def peak_and_fwhm(h, edges):
+    """(peak energy, FWHM) of histogram density h with bin edges ``edges``."""
+    h = np.asarray(h, dtype=np.float64)
+    centers = 0.5 * (edges[:-1] + edges[1:])
+    de = edges[1] - edges[0]
+    k = int(np.argmax(h))
+    peak = centers[k]
+    if 0 < k < h.size - 1:
+        y0, y1, y2 = h[k - 1], h[k], h[k + 1]
+        den = y0 - 2.0 * y1 + y2
+        if den != 0.0:
+            peak += 0.5 * de * (y0 - y2) / den
+    half = 0.5 * h[k]
+    i = k
+    while i > 0 and h[i - 1] >= half:
+        i -= 1
+    if i > 0:
+        left = centers[i - 1] + de * (half - h[i - 1]) / (h[i] - h[i - 1])
+    else:
+        left = centers[0]
+    j = k
+    while j < h.size - 1 and h[j + 1] >= half:
+        j += 1
+    if j < h.size - 1:
+        right = centers[j] + de * (h[j] - half) / (h[j] - h[j + 1])
+    else:
+        right = centers[-1]
+    return float(peak), float(right - left)

@@ -1,0 +1,194 @@
+"""Pins of the oracle pusher against facts the paper and the mathematics fix."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import analytic, pusher
+from workloads import random_push_inputs
+
+EPS = pusher.rr_coefficient(0.8)
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_rr_coefficient_value():
+    # Section 2: r_e ~ 2.8e-9 um, coefficient (4 pi / 3) r_e / lambda
+    assert EPS == pytest.approx(4.0 * np.pi / 3.0 * 2.8e-9 / 0.8, rel=1e-2)
+    assert 1.47e-8 < EPS < 1.48e-8
+
+
+def test_electric_kick_is_exact_without_b():
+    d = random_push_inputs(1, 500)
+    B = np.zeros_like(d["B"])
+    for qm in (-1.0, 1.0 / 1836.0):
+        u, _ = pusher.push(d["u"], d["E"], B, qm, 0.05, EPS, False)
+        np.testing.assert_allclose(u, d["u"] + qm * 0.05 * d["E"], rtol=1e-14, atol=1e-12)
+
+
+def _rodrigues(v, k, th):
+    k = k / np.linalg.norm(k)
+    return v * np.cos(th) + np.cross(k, v) * np.sin(th) + k * (k @ v) * (1 - np.cos(th))
+
+
+@pytest.mark.parametrize("qm", [-1.0, 1.0 / 1836.0])
+def test_boris_is_a_rotation_by_twice_atan(qm):
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        u = rng.normal(size=3) * 10.0
+        B = rng.normal(size=3) * 50.0
+        dt = 0.02
+        g = np.sqrt(1 + u @ u)
+        th = analytic.boris_rotation_angle(qm, np.linalg.norm(B), dt, g)
+        # charge of sign(qm) turns counter-clockwise about -sign(qm) B
+        expect = _rodrigues(u, -np.sign(qm) * B, th)
+        got, _ = pusher.push(u, np.zeros(3), B, qm, dt, EPS, False)
+        np.testing.assert_allclose(got, expect, rtol=1e-12, atol=1e-12)
+
+
+def test_gyration_preserves_energy_over_many_steps():
+    u = np.array([30.0, -4.0, 0.0])
+    B = np.array([0.0, 0.0, 120.0])
+    g0 = np.sqrt(1 + u @ u)
+    th = analytic.boris_rotation_angle(-1.0, 120.0, 0.01, g0)
+    for n in range(20000):
+        u, _ = pusher.push(u, np.zeros(3), B, -1.0, 0.01, EPS, False)
+    assert np.sqrt(1 + u @ u) == pytest.approx(g0, rel=1e-12)
+    u0 = np.array([30.0, -4.0, 0.0])
+    expect = _rodrigues(u0, np.array([0, 0, 120.0]), 20000 * th)
+    np.testing.assert_allclose(u, expect, rtol=1e-8, atol=1e-8)
+
+
+def test_rr_force_equals_nonderivative_ll_of_eq_3dll():
+    # Eq. (f_r), written with f_L, against the last two lines of Eq. (3dLL)
+    d = random_push_inputs(7, 2000)
+    fR = pusher.rr_force(d["E"], d["B"], d["u"], EPS)
+    g = pusher.gamma_of(d["u"])
+    v = d["u"] / g[:, None]
+    lorentz = -(d["E"] + np.cross(v, d["B"]))
+    ll = pusher.ll_nonderivative(d["E"], d["B"], d["u"], EPS) - lorentz
+    scale = np.linalg.norm(ll, axis=1) + EPS * np.linalg.norm(d["E"], axis=1) ** 2 + 1e-300
+    assert np.max(np.linalg.norm(fR - ll, axis=1) / scale) < 1e-9
+
+
+def test_damping_two_forms_agree_and_are_non_negative():
+    d = random_push_inputs(11, 2000)
+    de, dc = pusher.damping(d["E"], d["B"], d["u"], EPS)
+    g = pusher.gamma_of(d["u"])
+    scale = EPS * g * g * (np.sum(d["E"] ** 2, 1) + np.sum(d["B"] ** 2, 1))
+    assert np.max(np.abs(de - dc) / scale) < 1e-9
+    assert np.all(dc >= 0.0)
+
+
+def test_damping_limits_in_a_plane_wave():
+    # statements after Eq. (damping): E x B along +x; d -> 0 for v_x -> 1,
+    # d -> eps g^2 4 a0^2 for v_x -> -1, d -> eps g^2 a0^2 for v_perp^2 -> 1
+    a0 = 328.0
+    E, B = np.array([0, a0, 0.0]), np.array([0, 0, a0])
+    for g in (1e3, 1e5):
+        ub = np.sqrt(g * g - 1.0)
+        for u, lim in ((np.array([ub, 0, 0]), 0.0), (np.array([-ub, 0, 0]), 4.0),
+                       (np.array([0, ub, 0]), 1.0), (np.array([0, 0, ub]), 1.0)):
+            _, dc = pusher.damping(E, B, u, EPS)
+            assert dc / (EPS * g * g * a0 * a0) == pytest.approx(lim, abs=2.0 / g)
+
+
+def test_plane_wave_identities_used_by_the_closed_form():
+    rng = np.random.default_rng(5)
+    for _ in range(50):
+        Ey, Ez = rng.normal(size=2) * 100
+        E, B = np.array([0, Ey, Ez]), np.array([0, -Ez, Ey])
+        u = rng.normal(size=3) * 30
+        g = np.sqrt(1 + u @ u)
+        v = u / g
+        F = E + np.cross(v, B)
+        lhs = np.cross(F, B) + (v @ E) * E
+        np.testing.assert_allclose(lhs, [(1 - v[0]) * (Ey ** 2 + Ez ** 2), 0, 0], atol=1e-9)
+        h = g - u[0]
+        assert g * g * (F @ F - (v @ E) ** 2) == pytest.approx(h * h * (Ey ** 2 + Ez ** 2), rel=1e-9)
+
+
+def _run_plane_wave(wave, u0, dt, t_end, eps, rr):
+    orb = analytic.PlaneWaveOrbit(wave, u0, eps=eps, phi_span=4000.0)
+    _, u, _ = orb.at_time(-0.5 * dt)
+    x = np.zeros(3)
+    n = int(round(t_end / dt))
+    for k in range(n):
+        E, B = wave.fields(x[0], k * dt)
+        u, _ = pusher.push(u, E, B, -1.0, dt, EPS if rr else 0.0, rr)
+        x = x + dt * u / np.sqrt(1 + u @ u)
+    xa, ua, _ = orb.at_time(n * dt)
+    return x, u, xa, ua
+
+
+def _orbit_errors(eps, rr, dts, t_end=60.0):
+    wave = analytic.MonochromaticWave(40.0, 25.0)
+    u0 = np.array([-5.0, 1.0, 0.0])
+    errs = []
+    for dt in dts:
+        orb = analytic.PlaneWaveOrbit(wave, u0, eps=eps, phi_span=2000.0)
+        _, u, _ = orb.at_time(-0.5 * dt)
+        x = np.zeros(3)
+        n = int(round(t_end / dt))
+        for k in range(n):
+            E, B = wave.fields(x[0], k * dt)
+            u, _ = pusher.push(u, E, B, -1.0, dt, eps, rr)
+            x = x + dt * u / np.sqrt(1 + u @ u)
+        xa, ua, _ = orb.at_time(n * dt)
+        errs.append(abs(x[0] - xa))
+    orb0 = analytic.PlaneWaveOrbit(wave, u0, eps=0.0, phi_span=2000.0)
+    return errs, abs(orb0.at_time(t_end)[0] - xa)
+
+
+def test_plane_wave_orbit_lorentz_second_order():
+    errs, _ = _orbit_errors(0.0, False, (0.04, 0.02))
+    assert errs[0] / errs[1] == pytest.approx(4.0, rel=0.15)
+
+
+def test_plane_wave_orbit_with_rr_converges_to_exact_ll_solution():
+    # The mid-step estimate of Eq. (estim1) leaves out the RR increment, so the
+    # RR part is first order in dt with an error ~ eps^2: with strong
+    # (amplified) RR the scheme converges at first order, with weak RR the
+    # Boris second order shows.  In both cases it converges to the exact
+    # solution, and the error is far below the displacement caused by RR.
+    errs, effect = _orbit_errors(2e-4, True, (0.04, 0.02))
+    assert effect > 5.0
+    assert errs[1] < 1e-2 * effect
+    assert 1.7 < errs[0] / errs[1] < 2.6
+    errs, effect = _orbit_errors(2e-6, True, (0.02, 0.01))
+    assert effect > 1.0
+    assert errs[0] / errs[1] == pytest.approx(4.0, rel=0.15)
+
+
+def test_worked_example_displacement_error():
+    g = json.load(open(os.path.join(GOLDEN, "worked_example.json")))
+    wave = analytic.MonochromaticWave(g["a0"])
+    eps = pusher.rr_coefficient(g["lambda_um"])
+    x, u, xa, ua = _run_plane_wave(wave, np.array([g["p_x0"], 0, 0]), g["dt"], g["t_end"], eps, True)
+    rel = abs(x[0] - xa) / abs(xa)
+    assert rel <= g["rel_displacement_error_reported"]
+    # RR turned the electron round: it must end up moving with the wave
+    assert u[0] > 0 and xa > 0
+
+
+def test_radiative_cooling_in_uniform_b():
+    # gamma(t) = coth(eps B^2 t + atanh(1/gamma0)); amplified eps
+    eps, Bz, g0, t_end = 1e-4, 100.0, 50.0, 1.5
+    B = np.array([0, 0, Bz])
+    errs = []
+    for dt in (2e-4, 1e-4):
+        u = np.array([np.sqrt(g0 * g0 - 1.0), 0.0, 0.0])
+        n = int(round(t_end / dt))
+        # start at t = -dt/2 on the exact curve (direction is irrelevant for gamma)
+        gm = analytic.rr_cooling_gamma(-0.5 * dt, g0, Bz, eps)
+        u = u / np.linalg.norm(u) * np.sqrt(gm * gm - 1)
+        for _ in range(n):
+            u, _ = pusher.push(u, np.zeros(3), B, -1.0, dt, eps, True)
+        g = np.sqrt(1 + u @ u)
+        # after n pushes the stored momentum is u^{n-1/2}, at time (n - 1/2) dt
+        errs.append(abs(g - analytic.rr_cooling_gamma((n - 0.5) * dt, g0, Bz, eps)))
+    g_exact = analytic.rr_cooling_gamma(t_end, g0, Bz, eps)
+    assert g_exact < 0.5 * g0  # strong cooling happened
+    assert errs[1] < 1e-3 * g_exact
+    # strong RR: first order in dt (see the plane-wave test)
+    assert errs[0] / max(errs[1], 1e-300) > 1.7

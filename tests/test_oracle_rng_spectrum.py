@@ -1,0 +1,42 @@
+"""Pins of the oracle's SplitMix64 generator and spectrum peak/width helpers."""
+import numpy as np
+import pytest
+
+from oracle import rng, spectrum
+
+
+def test_splitmix64_published_known_answer():
+    # first output of SplitMix64 seeded with 0
+    assert int(rng.splitmix64(0, 0)) == 0xE220A8397B1DCDAF
+
+
+def test_splitmix64_stream_is_counter_based():
+    # output i of seed s equals output 0 of seed s + i * golden (mod 2^64)
+    for i in (1, 7, 12345):
+        s = (5 + i * 0x9E3779B97F4A7C15) % (1 << 64)
+        assert int(rng.splitmix64(5, i)) == int(rng.splitmix64(s, 0))
+
+
+def test_uniform24_is_uniform():
+    u = rng.uniform24(42, np.arange(200000))
+    assert u.min() >= 0.0 and u.max() < 1.0
+    assert np.all(u * 2 ** 24 == np.floor(u * 2 ** 24))
+    h, _ = np.histogram(u, bins=50, range=(0, 1))
+    chi2 = np.sum((h - 4000.0) ** 2 / 4000.0)
+    assert chi2 < 90.0  # 49 degrees of freedom, p ~ 5e-4
+
+
+def test_peak_and_fwhm_of_a_gaussian():
+    r = np.random.default_rng(0)
+    mu, sig = 120.0, 7.0
+    E = r.normal(mu, sig, size=2_000_000)
+    h, edges = spectrum.histogram(E, np.ones_like(E), 400, 250.0)
+    peak, width = spectrum.peak_and_fwhm(h, edges)
+    assert peak == pytest.approx(mu, abs=0.3)
+    assert width == pytest.approx(2 * np.sqrt(2 * np.log(2)) * sig, rel=0.02)
+
+
+def test_ion_energy_units():
+    # a proton with gamma = 2 carries m_p c^2 = 1836 * 0.511 MeV of kinetic energy
+    u = np.array([[np.sqrt(3.0), 0, 0]])
+    assert spectrum.ion_energies_mev(u, 1836.0)[0] == pytest.approx(1836 * 0.51099895)

@@ -1,0 +1,10 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This package holds no arithmetic of the method: it only names workload
+parameters (laser, foil, grid, particle counts) and draws seeded random
+test states.  Every derived quantity (cell size, time step, particle
+weight, radiation-reaction coefficient) is computed separately by each
+consumer from these raw parameters.
+"""
+from .configs import PRESETS, preset, periods_to_steps  # noqa: F401
+from .gen import random_push_inputs, random_particles, poisson_stream  # noqa: F401
