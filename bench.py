@@ -1,0 +1,163 @@
+"""Throughput benchmark of the PIC hot path on one MI355X.
+
+One step = push-deposit (gather, Boris, RR, move, integer deposit), field
+advance, the periodic cell sort, and (every --diag-every steps) the FP64
+energy budget and Gauss check.  Prints one JSON line.
+
+Workload (default): laser-foil run at the precision-form scale - LP a0 = 500,
+200 cells per wavelength, 100 wavelengths (20,000 cells), hydrogen foil of
+1 wavelength at n0 = 100 n_c with 25,000 particles per cell per species
+(1e7 particles), FP32 particles with compensated RR, FP64 reductions.  The
+warm-up steps carry the run into the laser-foil interaction (the pulse
+reaches the foil after 8 periods = 3,200 steps) before timing starts.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def alg_bytes_per_push(precision: str, compensated: bool, rr: bool):
+    """Algorithmic HBM bytes of one push (electron, ion): read cell, offset,
+    3 momenta, weight; write cell, offset, 3 momenta; compensated RR also
+    reads and writes 3 FP32 residuals per electron."""
+    r = 4 if precision == "fp32" else 8
+    ion = (4 + 5 * r) + (4 + 4 * r)
+    ele = ion + (24 if (precision == "fp32" and compensated and rr) else 0)
+    return ele, ion
+
+
+def time_run(cfg, steps, warmup, diag_every, timing=True):
+    import torch
+
+    from paper_1008_1685_amd import Run
+
+    run = Run(cfg)
+    run.step(warmup)
+    d0 = run.diag()
+    torch.cuda.synchronize()
+    run.timing(timing)
+    t0 = time.perf_counter()
+    done = 0
+    while done < steps:
+        k = min(diag_every, steps - done)
+        run.step(k)
+        done += k
+        if done % diag_every == 0 and done < steps:
+            run.diag()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = run.timing_read()
+    run.timing(False)
+    d1 = run.diag()
+    n_e = 0.5 * (d0["n_alive"][0] + d1["n_alive"][0])
+    n_i = 0.5 * (d0["n_alive"][1] + d1["n_alive"][1])
+    out = dict(seconds=t1 - t0, n_e=n_e, n_i=n_i, kernels=kt, diag0=d0, diag1=d1,
+               info=run.get_info())
+    run.close()
+    del run
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(cfg, budget_s=20.0, max_steps=8):
+    """The FP64 oracle, as is, on a bounded sample of the same workload."""
+    from oracle import pic as opic
+
+    sim = opic.Pic1D(cfg)
+    n = sim.sp[0]["xi"].size + sim.sp[1]["xi"].size
+    t0 = time.perf_counter()
+    k = 0
+    while k < max_steps and (time.perf_counter() - t0) < budget_s:
+        sim.step()
+        k += 1
+    dt = time.perf_counter() - t0
+    return dict(value=n * k / dt, unit="pushes/s", cores=1, kind="oracle",
+                sample=f"{k} oracle steps of the same workload from its initial state "
+                       f"({n} particles; numpy, single thread)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--warmup", type=int, default=4000)
+    ap.add_argument("--diag-every", type=int, default=1000)
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--no-side-runs", action="store_true",
+                    help="skip the RR-off and FP64 comparison runs and the CPU baseline")
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU particle decomposition is a design note, not built)", flush=True)
+        sys.exit(2)
+
+    import torch
+
+    from workloads import preset
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    cfg = preset(args.workload)
+    res = time_run(cfg, args.steps, args.warmup, args.diag_every)
+    pushes = (res["n_e"] + res["n_i"]) * args.steps
+    value = pushes / res["seconds"]
+    be, bi = alg_bytes_per_push(cfg["precision"], cfg["rr_compensated"], cfg["rr"])
+    push_ms, push_n = res["kernels"]["push"]
+    avg_push_s = push_ms * 1e-3 / max(push_n, 1)
+    bytes_per_launch = be * res["n_e"] + bi * res["n_i"]
+    achieved = bytes_per_launch / avg_push_s / 1e9
+    traffic = None
+    if os.path.exists(args.traffic_json):
+        try:
+            tj = json.load(open(args.traffic_json))
+            if tj.get("workload") == args.workload:
+                traffic = tj.get("bytes_per_launch")
+        except Exception:
+            traffic = None
+
+    line = dict(
+        metric="particle-pushes/s incl. RR+gather+deposit (% HBM roofline); p50/p99 run latency",
+        value=value, unit="pushes/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+        ms_per_step=res["seconds"] * 1e3 / args.steps, higher_is_better=True, scaling="weak",
+        vs_baseline=None, dtype="f32" if cfg["precision"] == "fp32" else "f64",
+        data="synthetic (seeded quiet-start foil, analytic laser)",
+        config=dict(workload=f"{args.workload}: LP a0={cfg['a0']:g}, {res['info']['n_cells']} cells, "
+                             f"{int(res['n_e'] + res['n_i'])} particles "
+                             f"({cfg['ppc']} per cell per species), "
+                             f"{cfg['precision']} + compensated RR, FP64 budgets",
+                    n_cells=res["info"]["n_cells"], particles=int(res["n_e"] + res["n_i"]),
+                    sort_interval=cfg["sort_interval"], diag_every=args.diag_every,
+                    t_start_periods=args.warmup * res["info"]["dt"] / (2 * 3.141592653589793),
+                    parallelism="single GPU"),
+        roofline=dict(bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s",
+                      frac=achieved / PEAK_HBM_GBS, traffic=traffic,
+                      kernel="k_push", bytes_per_launch=bytes_per_launch,
+                      avg_launch_us=avg_push_s * 1e6, alg_bytes_per_push=dict(electron=be, ion=bi)),
+        kernel_ms_per_step={k: v[0] / max(args.steps, 1) for k, v in res["kernels"].items()},
+        energy_balance=res["diag1"]["balance"] / max(res["diag1"]["E_in"], 1e-300),
+        gauss_int=res["diag1"]["gauss_int"],
+    )
+    if not args.no_side_runs:
+        side = max(args.steps // 4, 200)
+        r_off = time_run(dict(cfg, rr=False), side, args.warmup, args.diag_every, timing=True)
+        r_64 = time_run(dict(cfg, precision="fp64"), side, args.warmup, args.diag_every, timing=True)
+        v_off = (r_off["n_e"] + r_off["n_i"]) * side / r_off["seconds"]
+        v_64 = (r_64["n_e"] + r_64["n_i"]) * side / r_64["seconds"]
+        line["rr_cost"] = dict(pushes_per_s_rr_off=v_off, overhead=v_off / value - 1.0,
+                               paper="about +10% compute time with RR (Section 3)")
+        line["fp64_path"] = dict(pushes_per_s=v_64, speedup_fp32_over_fp64=value / v_64)
+        line["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,232 @@
+/*
+ * pic.h - C ABI of the MI355X (gfx950) 1D3V particle-in-cell hot path with
+ * radiation reaction, after Tamburini et al., "Radiation Reaction Effects on
+ * Radiation Pressure Acceleration".
+ *
+ * What one step computes (pic_step):
+ *   1. gather E^n, B^n at every particle by linear weighting on a 1D Yee grid;
+ *   2. Boris push for the Lorentz force, u^{n-1/2} -> u_L^{n+1/2} (Section 3);
+ *   3. for electrons, the radiation-reaction force of Eq. (f_r), evaluated at
+ *      the mid-step estimate of Eqs. (estim1), (estimgamma), added by the
+ *      leapfrog superposition of Eq. (pertfull): u^{n+1/2} = u_L + dt f_R;
+ *   4. leapfrog move x^{n+1} = x^n + dt u^{n+1/2} / gamma^{n+1/2};
+ *   5. charge-conserving current deposition in 64-bit fixed point;
+ *   6. Yee field advance with laser injection at x = 0 and absorbing ends;
+ *   7. every sort_interval steps, a counting sort of particles by cell.
+ * The grid, shape, deposition, solver and boundaries are not specified by
+ * the paper ("a standard PIC code", Section 3); the choices are documented
+ * with each entry point and in the library's design notes.
+ *
+ * Units (Section 2): t in 1/omega, x in c/omega, momentum in m c, fields in
+ * m omega c/|e|, densities in n_c.  One laser wavelength = one period = 2 pi.
+ *
+ * Conventions for every entry point:
+ *   - Return value: PIC_OK (0) or a negative pic_status; no C++ exception
+ *     crosses the ABI.  On error pic_last_error() returns a thread-local
+ *     message describing the first failure.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Entry points marked "async" only enqueue work on it; "blocking" ones
+ *     synchronise it before returning.  Errors of asynchronous work surface
+ *     at the next blocking call.
+ *   - The library never allocates device memory: the caller owns one
+ *     device workspace per run (size from pic_workspace_bytes), keeps it
+ *     alive until pic_free, and owns the stream.  A pic_run handle owns only
+ *     host metadata.
+ *   - A run is not thread-safe; different runs may be used from different
+ *     threads.
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PIC_ABI_VERSION 1
+
+typedef enum pic_status {
+  PIC_OK = 0,
+  PIC_EINVAL = -1,     /* invalid argument or configuration */
+  PIC_ENOMEM = -2,     /* workspace too small / capacity exceeded */
+  PIC_EHIP = -3,       /* HIP runtime error */
+  PIC_ENONFINITE = -4, /* a particle momentum or position became NaN/Inf */
+  PIC_EBUSY = -5       /* no free slot in a batch */
+} pic_status;
+
+enum pic_precision { PIC_FP32 = 0, PIC_FP64 = 1 };
+enum pic_polarisation { PIC_LP = 0, PIC_CP = 1 };
+
+/* Run configuration (caller-owned, copied by pic_init).
+ * Geometry: box of box_lambda wavelengths, cells_per_lambda cells per
+ * wavelength (n_cells = round(box_lambda * cells_per_lambda)), dt = cfl*dx
+ * with 0 < cfl <= 0.5 so that no particle crosses more than one cell edge.
+ * Laser (Section 4): enters at x = 0 from t = 0; LP: E_y = a0 f(t) sin t;
+ * CP: E_y = (a0/sqrt2) f sin t, E_z = (a0/sqrt2) f cos t (same intensity for
+ * the same a0); f = sin^2 rise over t_rise periods, 1 for t_flat periods,
+ * sin^2 fall over t_fall periods.
+ * Foil (Section 4): electrons and protons (mass_ratio electron masses),
+ * density n0 n_c, front at x_foil wavelengths, thickness wavelengths; ppc
+ * particles per cell per species on a quiet start (offsets ((k + 1/2) +
+ * jitter (U - 1/2)) / ppc, U the SplitMix64 output number i of the stream
+ * seeded with `seed`, i the particle index; both species share positions),
+ * cold, weight n0 dx / ppc.
+ * Radiation reaction (Section 3): on electrons when rr != 0, with strength
+ * (4 pi / 3) r_e / lambda for the wavelength lambda_um in micrometres.
+ * rr_compensated (fp32 only): the RR increment is added with a
+ * compensated (TwoSum) sum whose rounding residual is carried per particle. */
+typedef struct pic_config {
+  uint32_t struct_size;      /* sizeof(pic_config) of the caller */
+  int32_t precision;         /* PIC_FP32 or PIC_FP64 storage and arithmetic */
+  double lambda_um;          /* laser wavelength in micrometres (> 0) */
+  int32_t cells_per_lambda;  /* >= 4 */
+  int32_t ppc;               /* particles per cell per species (>= 1) */
+  double box_lambda;         /* box length in wavelengths */
+  double cfl;                /* dt / dx, in (0, 0.5] */
+  int32_t pol;               /* PIC_LP or PIC_CP */
+  int32_t rr;                /* radiation reaction on electrons (0/1) */
+  double a0;                 /* normalised laser amplitude */
+  double t_rise, t_flat, t_fall; /* envelope, in periods */
+  double n0;                 /* foil density in n_c */
+  double x_foil;             /* foil front, wavelengths */
+  double thickness;          /* foil thickness, wavelengths */
+  double mass_ratio;         /* ion / electron mass (ion charge +1) */
+  int32_t rr_compensated;    /* 0/1, fp32 only */
+  int32_t sort_interval;     /* steps between sorts (>= 1) */
+  uint64_t seed;             /* quiet-start jitter seed */
+  double jitter;             /* jitter amplitude in units of the spacing, [0, 1] */
+  int64_t capacity;          /* particles per species to reserve; 0 = foil count */
+} pic_config;
+
+/* Run constants derived by pic_init (read-only). */
+typedef struct pic_info {
+  int32_t n_cells;
+  int32_t precision;
+  double dx, dt, eps_rr, w_ref;
+  int64_t capacity;          /* per species */
+  int64_t n_init[2];         /* particles per species after pic_init */
+  int64_t step;              /* steps enqueued so far */
+  int32_t tile;              /* particles per push work-group */
+  int32_t window;            /* LDS deposit window, in nodes */
+} pic_info;
+
+/* Diagnostics at the current step n (particles at x^n with u^{n-1/2},
+ * fields E^n, B^n).  Energies are in units of m^2 omega^2 c^2 / (4 pi e^2)
+ * per unit transverse area (field: sum of field^2/2 dx; particle:
+ * sum of w M (gamma - 1)); all reductions in FP64. */
+typedef struct pic_diag_out {
+  int64_t step;
+  double t;
+  int64_t n_alive[2];        /* electrons, ions */
+  double U_Ex, U_Et, U_B;    /* longitudinal E, transverse E, B field energy */
+  double K_e, K_i;           /* kinetic energy from u^{n-1/2} */
+  double E_rad;              /* cumulative RR loss, sum w (gamma_L - gamma^{n+1/2}) */
+  double E_in;               /* cumulative incident laser energy at x = 0 */
+  double E_out_left, E_out_right; /* cumulative outgoing field energy */
+  double E_esc;              /* cumulative kinetic energy of removed particles */
+  double gauss;              /* max |dEx/dx - rho| over nodes 1..n-1 (field units) */
+  int64_t gauss_int;         /* the same residual in the integer units (expect 0) */
+  int64_t n_stiff;           /* RR pushes with dt|f_R| > 0.1 |u_L| (cumulative) */
+  int32_t nonfinite;         /* 1 if a NaN/Inf particle was seen */
+  int32_t reserved;
+} pic_diag_out;
+
+/* Host-side particle and field state for pic_get_state / pic_set_state.
+ * Arrays of type `real` are float for PIC_FP32 runs and double for PIC_FP64.
+ * Any pointer may be NULL to skip that array (get) or leave it unchanged
+ * (set; particle arrays must then all be given or all be NULL).
+ * Grid layout: node i (x = i dx, i = 0..n) for Ey, Ez; half-node h
+ * (x = (h - 1/2) dx, h = 0..n+1, h = 0 and n+1 are boundary guards) for
+ * Ex, By, Bz.  Integer currents: Jx_int on half-nodes (n + 2 entries),
+ * Jy_int, Jz_int on nodes -1..n+1 stored at index node + 1 (n + 3 entries);
+ * Ex_int on half-nodes (n + 2).  Fixed-point scale: Ex = Ex_int w_ref 2^-32,
+ * Jx = Jx_int w_ref 2^-32 / dt, Jy = Jy_int w_ref 2^-32 / dx. */
+typedef struct pic_species_state {
+  int64_t count;             /* get: alive count after compaction; set: count */
+  int32_t* cell;             /* [count] cell index, 0..n-1 */
+  void* off;                 /* [count] real offset in [0, 1) */
+  void* ux; void* uy; void* uz; /* [count] real momentum u^{n-1/2} (p / M c) */
+  void* w;                   /* [count] real weight (density x length) */
+  float* rx; float* ry; float* rz; /* [count] fp32 RR residuals (electrons) */
+} pic_species_state;
+
+typedef struct pic_state {
+  pic_species_state sp[2];
+  void* Ex; void* Ey; void* Ez; void* By; void* Bz; /* real arrays, see above */
+  int64_t* Ex_int;           /* [n + 2] */
+  int64_t* Jx_int;           /* [n + 2] current deposited at the current step */
+  int64_t* Jy_int;           /* [n + 3] */
+  int64_t* Jz_int;           /* [n + 3] */
+  int64_t step;              /* step counter n (set: also sets the laser clock) */
+} pic_state;
+
+/* Workspace bytes a run with `cfg` needs (host-only; no GPU access). */
+pic_status pic_workspace_bytes(const pic_config* cfg, size_t* bytes);
+
+/* Validate cfg, carve the caller's device workspace d_ws (ws_bytes bytes,
+ * 256-byte aligned) and initialise the quiet-start foil, zero fields and
+ * budgets.  Async on `stream`.  On success *out is a new handle. */
+pic_status pic_init(const pic_config* cfg, void* d_ws, size_t ws_bytes,
+                    void* stream, struct pic_run** out);
+
+/* Enqueue n_steps full steps (push-deposit, field advance, periodic sort).
+ * Async.  Particles leaving [0, n dx) are removed. */
+pic_status pic_step(struct pic_run* run, int64_t n_steps, void* stream);
+
+/* Compute diagnostics on the device (FP64), copy them to *out.  Blocking.
+ * Returns PIC_ENONFINITE (with *out filled) if a non-finite particle was
+ * seen since pic_init. */
+pic_status pic_diag(struct pic_run* run, pic_diag_out* out, void* stream);
+
+/* Copy run constants. Host-only. */
+pic_status pic_get_info(const struct pic_run* run, pic_info* out);
+
+/* Release host metadata; the workspace stays owned by the caller. */
+void pic_free(struct pic_run* run);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* pic_last_error(void);
+
+/* Stage entry points (one kernel each), for tests and profiling.  Async.
+ *   pic_push_deposit: steps 1-5 for every particle; leaves J_int of this
+ *     push in the run (readable with pic_get_state) and does not advance
+ *     the fields or the step counter.
+ *   pic_field_advance: step 6 with the J_int left by the last push; advances
+ *     the step counter.
+ *   pic_sort: step 7 now (compacts removed particles). */
+pic_status pic_push_deposit(struct pic_run* run, void* stream);
+pic_status pic_field_advance(struct pic_run* run, void* stream);
+pic_status pic_sort(struct pic_run* run, void* stream);
+
+/* Checkpoint / test I/O of the full state (host buffers).  Blocking.
+ * Particle arrays given to pic_get_state must hold `capacity` entries
+ * (pic_get_info); removed particles are skipped, so counts are alive counts.
+ * pic_set_state validates cells and offsets, replaces the particle arrays
+ * (count <= capacity; the current buffers of both parities are cleared when
+ * particles are replaced) and/or fields, Ex_int and the current buffers of
+ * the current step; step >= 0 also resets the step counter. */
+pic_status pic_get_state(struct pic_run* run, pic_state* st, void* stream);
+pic_status pic_set_state(struct pic_run* run, const pic_state* st, void* stream);
+
+/* Ion energy spectrum (Section 4 spectra): weighted histogram of proton
+ * kinetic energy (gamma - 1) mass_ratio 0.51099895 MeV in `bins` bins on
+ * [0, e_max_mev), weights summed exactly in fixed point; host_hist gets
+ * protons per MeV (weight / bin width).  Blocking. */
+pic_status pic_spectrum(struct pic_run* run, int32_t bins, double e_max_mev,
+                        double* host_hist, void* stream);
+
+/* Per-kernel timing for profiling: when enabled, pic_step records HIP
+ * events around each kernel it launches.  pic_timing_read synchronises the
+ * stream and returns accumulated milliseconds and launch counts for
+ * kernel k = 0 push-deposit, 1 field advance, 2 sort (all passes). */
+pic_status pic_timing_enable(struct pic_run* run, int32_t enable);
+pic_status pic_timing_read(struct pic_run* run, double ms[3], int64_t launches[3],
+                           void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIC_H */

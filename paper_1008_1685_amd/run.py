@@ -1,0 +1,200 @@
+"""Python handle over one simulation run of the C ABI (argument marshalling only).
+
+Device memory comes from torch (one uint8 workspace tensor per run) and
+work is enqueued on torch's current HIP stream; every computation happens
+in the library's kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _native as N
+
+_CFG_KEYS = ("lambda_um", "cells_per_lambda", "ppc", "box_lambda", "cfl", "a0", "t_rise",
+             "t_flat", "t_fall", "n0", "x_foil", "thickness", "mass_ratio", "sort_interval",
+             "seed", "jitter")
+
+
+def make_config(cfg: dict, capacity: int = 0) -> N.PicConfig:
+    c = N.PicConfig()
+    c.struct_size = C.sizeof(N.PicConfig)
+    c.precision = N.PIC_FP64 if cfg.get("precision", "fp32") == "fp64" else N.PIC_FP32
+    for k in _CFG_KEYS:
+        setattr(c, k, type(getattr(c, k))(cfg[k]))
+    c.pol = N.PIC_CP if cfg["pol"] == "CP" else N.PIC_LP
+    c.rr = 1 if cfg["rr"] else 0
+    c.rr_compensated = 1 if cfg.get("rr_compensated", True) else 0
+    c.capacity = int(capacity)
+    return c
+
+
+def workspace_bytes(cfg: dict, capacity: int = 0) -> int:
+    lib = N.load()
+    c = make_config(cfg, capacity)
+    n = C.c_size_t(0)
+    N.check(lib.pic_workspace_bytes(C.byref(c), C.byref(n)), "pic_workspace_bytes")
+    return int(n.value)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+class Run:
+    """One laser-foil run resident on the GPU."""
+
+    def __init__(self, cfg: dict, capacity: int = 0, device: str = "cuda", workspace=None):
+        import torch
+
+        self.lib = N.load()
+        self.cfg = dict(cfg)
+        self._c = make_config(cfg, capacity)
+        self.ws_bytes = workspace_bytes(cfg, capacity)
+        if workspace is None:
+            workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        elif workspace.numel() * workspace.element_size() < self.ws_bytes:
+            raise ValueError("workspace tensor too small")
+        self.ws = workspace
+        self._h = C.c_void_p()
+        N.check(self.lib.pic_init(C.byref(self._c), C.c_void_p(self.ws.data_ptr()),
+                                  C.c_size_t(self.ws_bytes), self._stream(), C.byref(self._h)),
+                "pic_init")
+        self.info = self.get_info()
+        self.rdt = np.float32 if self.info["precision"] == N.PIC_FP32 else np.float64
+
+    @staticmethod
+    def _stream():
+        import torch
+
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def close(self):
+        if self._h:
+            self.lib.pic_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ stepping
+    def step(self, n: int = 1):
+        N.check(self.lib.pic_step(self._h, int(n), self._stream()), "pic_step")
+
+    def push_deposit(self):
+        N.check(self.lib.pic_push_deposit(self._h, self._stream()), "pic_push_deposit")
+
+    def field_advance(self):
+        N.check(self.lib.pic_field_advance(self._h, self._stream()), "pic_field_advance")
+
+    def sort(self):
+        N.check(self.lib.pic_sort(self._h, self._stream()), "pic_sort")
+
+    # ------------------------------------------------------------ inspection
+    def get_info(self) -> dict:
+        o = N.PicInfo()
+        N.check(self.lib.pic_get_info(self._h, C.byref(o)), "pic_get_info")
+        return dict(n_cells=o.n_cells, precision=o.precision, dx=o.dx, dt=o.dt, eps_rr=o.eps_rr,
+                    w_ref=o.w_ref, capacity=o.capacity, n_init=(o.n_init[0], o.n_init[1]),
+                    step=o.step, tile=o.tile, window=o.window)
+
+    def diag(self, allow_nonfinite: bool = False) -> dict:
+        o = N.PicDiagOut()
+        st = self.lib.pic_diag(self._h, C.byref(o), self._stream())
+        if not (allow_nonfinite and st == N.PIC_ENONFINITE):
+            N.check(st, "pic_diag")
+        d = {k: getattr(o, k) for k, _ in N.PicDiagOut._fields_ if k != "reserved"}
+        d["n_alive"] = (o.n_alive[0], o.n_alive[1])
+        d["U_field"] = o.U_Ex + o.U_Et + o.U_B
+        d["balance"] = (d["U_field"] + o.K_e + o.K_i + o.E_rad + o.E_out_left + o.E_out_right
+                        + o.E_esc - o.E_in)
+        return d
+
+    def get_state(self, residuals: bool = True) -> dict:
+        info = self.get_info()
+        n, cap, rdt = info["n_cells"], info["capacity"], self.rdt
+        st = N.PicState()
+        out = {}
+        keep = []
+        for s in range(2):
+            arrs = dict(cell=np.empty(cap, np.int32), off=np.empty(cap, rdt), ux=np.empty(cap, rdt),
+                        uy=np.empty(cap, rdt), uz=np.empty(cap, rdt), w=np.empty(cap, rdt))
+            if s == 0 and residuals:
+                for k in ("rx", "ry", "rz"):
+                    arrs[k] = np.empty(cap, np.float32)
+            sp = st.sp[s]
+            for k, a in arrs.items():
+                setattr(sp, k, _ptr(a))
+            out[s] = arrs
+            keep.append(arrs)
+        f = dict(Ex=np.empty(n + 2, rdt), Ey=np.empty(n + 1, rdt), Ez=np.empty(n + 1, rdt),
+                 By=np.empty(n + 2, rdt), Bz=np.empty(n + 2, rdt), Ex_int=np.empty(n + 2, np.int64),
+                 Jx_int=np.empty(n + 2, np.int64), Jy_int=np.empty(n + 3, np.int64),
+                 Jz_int=np.empty(n + 3, np.int64))
+        for k, a in f.items():
+            setattr(st, k, _ptr(a))
+        N.check(self.lib.pic_get_state(self._h, C.byref(st), self._stream()), "pic_get_state")
+        res = dict(f)
+        res["step"] = st.step
+        for s in range(2):
+            cnt = st.sp[s].count
+            res[f"sp{s}"] = {k: a[:cnt].copy() for k, a in out[s].items()}
+        return res
+
+    def set_state(self, particles: dict | None = None, fields: dict | None = None,
+                  step: int = -1):
+        """particles: {0: {...}, 1: {...}} with cell, off, ux, uy, uz, w (+ rx, ry, rz);
+        fields: any of Ex, Ey, Ez, By, Bz, Ex_int."""
+        st = N.PicState()
+        keep = []
+        for s in range(2):
+            sp = st.sp[s]
+            p = (particles or {}).get(s)
+            if p is None:
+                sp.count = 0
+                continue
+            sp.count = len(p["cell"])
+            for k in ("cell", "off", "ux", "uy", "uz", "w", "rx", "ry", "rz"):
+                if k not in p:
+                    continue
+                if len(p[k]) != sp.count:
+                    raise ValueError(f"species {s}: {k} has {len(p[k])} entries, cell has {sp.count}")
+                dt = np.int32 if k == "cell" else (np.float32 if k in ("rx", "ry", "rz") else self.rdt)
+                a = np.ascontiguousarray(p[k], dtype=dt)
+                keep.append(a)
+                setattr(sp, k, _ptr(a))
+        n = self.info["n_cells"]
+        need = dict(Ex=n + 2, Ey=n + 1, Ez=n + 1, By=n + 2, Bz=n + 2, Ex_int=n + 2,
+                    Jx_int=n + 2, Jy_int=n + 3, Jz_int=n + 3)
+        for k, v in (fields or {}).items():
+            if k not in need:
+                raise KeyError(f"unknown field {k!r}")
+            dt = np.int64 if k in ("Ex_int", "Jx_int", "Jy_int", "Jz_int") else self.rdt
+            a = np.ascontiguousarray(v, dtype=dt)
+            if a.shape != (need[k],):
+                raise ValueError(f"{k} must have shape ({need[k]},), got {a.shape}")
+            keep.append(a)
+            setattr(st, k, _ptr(a))
+        st.step = int(step)
+        N.check(self.lib.pic_set_state(self._h, C.byref(st), self._stream()), "pic_set_state")
+
+    def spectrum(self, bins: int, e_max_mev: float) -> np.ndarray:
+        h = np.zeros(bins, np.float64)
+        N.check(self.lib.pic_spectrum(self._h, int(bins), float(e_max_mev),
+                                      h.ctypes.data_as(C.POINTER(C.c_double)), self._stream()),
+                "pic_spectrum")
+        return h
+
+    # ------------------------------------------------------------ timing
+    def timing(self, enable: bool):
+        N.check(self.lib.pic_timing_enable(self._h, 1 if enable else 0), "pic_timing_enable")
+
+    def timing_read(self):
+        ms = (C.c_double * 3)()
+        nl = (C.c_int64 * 3)()
+        N.check(self.lib.pic_timing_read(self._h, ms, nl, self._stream()), "pic_timing_read")
+        return {k: (ms[i], nl[i]) for i, k in enumerate(("push", "field", "sort"))}

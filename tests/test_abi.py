@@ -1,0 +1,64 @@
+"""The C-ABI library loads and exports every entry point include/pic.h declares
+(no GPU needed: nothing here launches a kernel)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1008_1685_amd import _native as N
+from workloads import preset
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "pic.h")).read()
+    return sorted(set(re.findall(r"\b(pic_[a-z_]+)\s*\(", txt)))
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    lib = N.load()
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in N.SIGNATURES, f"{n} not declared in the binding"
+
+
+def test_struct_layouts_match_header_sizes():
+    # pic_config: validated by struct_size; a wrong layout is rejected
+    lib = N.load()
+    c = N.PicConfig()
+    c.struct_size = C.sizeof(N.PicConfig) + 8
+    n = C.c_size_t()
+    assert lib.pic_workspace_bytes(C.byref(c), C.byref(n)) == N.PIC_EINVAL
+    assert b"struct_size" in lib.pic_last_error()
+
+
+def test_workspace_bytes_and_validation_on_host():
+    from paper_1008_1685_amd.run import make_config
+    lib = N.load()
+    sizes = {}
+    for name in ("c1", "c2", "c3"):
+        c = make_config(preset(name))
+        n = C.c_size_t()
+        assert lib.pic_workspace_bytes(C.byref(c), C.byref(n)) == N.PIC_OK
+        sizes[name] = n.value
+    assert sizes["c1"] < sizes["c2"] < sizes["c3"]
+    # c3: 5e6 particles per species, two buffers, 24 B + 12 B residuals (electrons)
+    assert sizes["c3"] > 2 * 5e6 * (24 + 12 + 24)
+    for bad in (dict(cfl=0.6), dict(ppc=0), dict(x_foil=99.0), dict(cells_per_lambda=2)):
+        c = make_config(preset("c1", **bad))
+        assert lib.pic_workspace_bytes(C.byref(c), C.byref(n)) == N.PIC_EINVAL
+
+
+def test_null_arguments_are_rejected_without_a_gpu():
+    lib = N.load()
+    assert lib.pic_step(None, 1, None) == N.PIC_EINVAL
+    assert lib.pic_diag(None, None, None) == N.PIC_EINVAL
+    c = N.PicConfig()
+    h = C.c_void_p()
+    from paper_1008_1685_amd.run import make_config
+    c = make_config(preset("c1"))
+    assert lib.pic_init(C.byref(c), None, 0, None, C.byref(h)) == N.PIC_EINVAL

@@ -7,4 +7,4 @@ weight, radiation-reaction coefficient) is computed separately by each
 consumer from these raw parameters.
 """
 from .configs import PRESETS, preset, periods_to_steps  # noqa: F401
-from .gen import random_push_inputs, random_particles, poisson_stream  # noqa: F401
+from .gen import random_push_inputs, random_particles, random_fields, poisson_stream  # noqa: F401
