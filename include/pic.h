@@ -109,7 +109,7 @@ typedef struct pic_info {
   int64_t n_init[2];         /* particles per species after pic_init */
   int64_t step;              /* steps enqueued so far */
   int32_t tile;              /* particles per push work-group */
-  int32_t window;            /* LDS deposit window, in nodes */
+  int32_t lds_slots;         /* 64-bit LDS current accumulators per push work-group */
 } pic_info;
 
 /* Diagnostics at the current step n (particles at x^n with u^{n-1/2},

@@ -58,7 +58,7 @@ class PicInfo(C.Structure):
         ("n_init", C.c_int64 * 2),
         ("step", C.c_int64),
         ("tile", C.c_int32),
-        ("window", C.c_int32),
+        ("lds_slots", C.c_int32),
     ]
 
 

@@ -28,8 +28,8 @@ constexpr int kDead = INT_MIN;        // cell index of a removed particle
 constexpr int kThreads = 256;         // push work-group
 constexpr int kPPT = 8;               // particles per thread per tile
 constexpr int kTile = kThreads * kPPT;
-constexpr int kNW = 16;               // LDS deposit window (storage indices)
-constexpr int kLanes = 64;            // wavefront width; one LDS copy per lane
+constexpr int kLdsSlots = 3072;       // 64-bit LDS current accumulators per work-group (24 KB)
+constexpr int kLanes = 64;            // wavefront width
 constexpr int kFieldChunk = 256;      // nodes per field work-group
 constexpr int kTwo24 = 1 << 24;
 
@@ -132,12 +132,19 @@ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
   e = (a - (s - bb)) + (b - bb);
 }
 
+// Current accumulation of one push work-group: an LDS window of W storage
+// indices (starting at wlo) covering every node the tile's particles can
+// touch, with R = 2^rshift private copies per slot (lane & (R - 1) picks
+// the copy), so lanes of a wave that hit the same node add to different
+// words.  Tiles whose window does not fit use global atomics instead.
 struct DepositCtx {
-  unsigned long long* lds;  // [3][kNW][kLanes]
+  unsigned long long* lds;  // [3][W][R]
   unsigned long long* J[3];
-  int wlo;                  // storage index of window slot 0
-  int lane;
-  int jmin, jmax;           // window slots touched by this thread
+  int wlo;
+  int W;
+  int rshift;
+  int copy;
+  bool use_lds;
 };
 
 // Integer current of one move (cell c, offset o) -> (c1, o1); see the
@@ -166,24 +173,22 @@ __device__ __forceinline__ void deposit(DepositCtx& d, int c, R o, int c1, R o1,
   const long long jz1 = (long long)qw * ((vz24 * (wo1 + wn1)) >> 25);
   const bool moved = (c1 != c);
   const int j0 = base + 1;  // Jx half-node base+1/2 and Jy node base share index base+1
-  const int r = j0 - d.wlo;
-  if (r >= 0 && r + 2 < kNW) {
-    unsigned long long* L = d.lds + d.lane;
-    atomicAdd(L + ((0 * kNW + r) << 6), (unsigned long long)jx0);
-    atomicAdd(L + ((1 * kNW + r) << 6), (unsigned long long)jy0);
-    atomicAdd(L + ((1 * kNW + r + 1) << 6), (unsigned long long)jy1);
-    atomicAdd(L + ((2 * kNW + r) << 6), (unsigned long long)jz0);
-    atomicAdd(L + ((2 * kNW + r + 1) << 6), (unsigned long long)jz1);
-    d.jmin = min(d.jmin, r);
-    d.jmax = max(d.jmax, r + 1);
+  if (d.use_lds) {
+    const int r = j0 - d.wlo;  // 0 <= r <= W - 3 by construction of the window
+    unsigned long long* L = d.lds + d.copy;
+    const int W = d.W, sh = d.rshift;
+    atomicAdd(L + ((0 * W + r) << sh), (unsigned long long)jx0);
+    atomicAdd(L + ((1 * W + r) << sh), (unsigned long long)jy0);
+    atomicAdd(L + ((1 * W + r + 1) << sh), (unsigned long long)jy1);
+    atomicAdd(L + ((2 * W + r) << sh), (unsigned long long)jz0);
+    atomicAdd(L + ((2 * W + r + 1) << sh), (unsigned long long)jz1);
     if (moved) {
       const long long jx1 = (long long)qw * F1;
       const long long jy2 = (long long)qw * ((vy24 * (wo2 + wn2)) >> 25);
       const long long jz2 = (long long)qw * ((vz24 * (wo2 + wn2)) >> 25);
-      atomicAdd(L + ((0 * kNW + r + 1) << 6), (unsigned long long)jx1);
-      atomicAdd(L + ((1 * kNW + r + 2) << 6), (unsigned long long)jy2);
-      atomicAdd(L + ((2 * kNW + r + 2) << 6), (unsigned long long)jz2);
-      d.jmax = max(d.jmax, r + 2);
+      atomicAdd(L + ((0 * W + r + 1) << sh), (unsigned long long)jx1);
+      atomicAdd(L + ((1 * W + r + 2) << sh), (unsigned long long)jy2);
+      atomicAdd(L + ((2 * W + r + 2) << sh), (unsigned long long)jz2);
     }
   } else {
     atomicAdd(d.J[0] + j0, (unsigned long long)jx0);
@@ -209,8 +214,7 @@ struct PushAcc {
 // One particle: gather, Boris, RR, move, deposit, store.
 template <typename R, bool RR, bool COMP>
 __device__ __forceinline__ void push_particle(const PushArgs<R>& a, const SpeciesDev<R>& sp,
-                                              int s, int i, DepositCtx& dc, PushAcc& acc) {
-  const int c = sp.cell[i];
+                                              int s, int i, int c, DepositCtx& dc, PushAcc& acc) {
   if (c == kDead) return;
   const R o = sp.off[i];
   const R ux = sp.ux[i], uy = sp.uy[i], uz = sp.uz[i];
@@ -331,47 +335,59 @@ __device__ __forceinline__ void push_particle(const PushArgs<R>& a, const Specie
 template <typename R, bool RR, bool COMP>
 __device__ __forceinline__ void push_tile(const PushArgs<R>& a, int s, int tile, int n, int base,
                                           unsigned long long* lds) {
-  __shared__ int s_lo, s_hi;
+  __shared__ int s_mn[kThreads / kLanes], s_mx[kThreads / kLanes];
   __shared__ double s_red[3][kThreads / kLanes];
   const SpeciesDev<R> sp = a.sp[s];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
 
-  // window centred on the cell of the tile's middle particle
-  const int mid = min(base + kTile / 2, n - 1);
-  const int anchor = sp.cell[mid];
+  // cells of this thread's particles and the tile's cell range
+  int cl[kPPT];
+  int cmin = INT_MAX, cmax = INT_MIN;
+#pragma unroll
+  for (int k = 0; k < kPPT; ++k) {
+    const int i = base + k * kThreads + tid;
+    cl[k] = i < n ? sp.cell[i] : kDead;
+    if (cl[k] != kDead) {
+      cmin = min(cmin, cl[k]);
+      cmax = max(cmax, cl[k]);
+    }
+  }
+  cmin = wave_min(cmin);
+  cmax = wave_max(cmax);
+  if (lane == 0) {
+    s_mn[wid] = cmin;
+    s_mx[wid] = cmax;
+  }
+  __syncthreads();
+  cmin = min(min(s_mn[0], s_mn[1]), min(s_mn[2], s_mn[3]));
+  cmax = max(max(s_mx[0], s_mx[1]), max(s_mx[2], s_mx[3]));
+  if (cmin > cmax) return;  // every particle of the tile was removed
+
+  // window: storage indices cmin .. cmax + 3 (nodes cmin - 1 .. cmax + 2)
   DepositCtx dc;
   dc.lds = lds;
   dc.J[0] = a.J[0];
   dc.J[1] = a.J[1];
   dc.J[2] = a.J[2];
-  dc.wlo = anchor == kDead ? INT_MIN / 2 : anchor + 2 - kNW / 2;
-  dc.lane = lane;
-  dc.jmin = INT_MAX;
-  dc.jmax = INT_MIN;
-
-  {
-    ulonglong2* z = reinterpret_cast<ulonglong2*>(lds);
-    for (int e = tid; e < 3 * kNW * kLanes / 2; e += kThreads) z[e] = make_ulonglong2(0, 0);
-  }
-  if (tid == 0) {
-    s_lo = INT_MAX;
-    s_hi = INT_MIN;
-  }
+  dc.wlo = cmin;
+  dc.W = cmax - cmin + 4;
+  int sh = 6;
+  while (sh > 0 && 3 * dc.W * (1 << sh) > kLdsSlots) --sh;
+  dc.rshift = sh;
+  dc.copy = lane & ((1 << sh) - 1);
+  const int E = 3 * dc.W * (1 << sh);
+  dc.use_lds = E <= kLdsSlots;
+  if (dc.use_lds)
+    for (int e = tid; e < E; e += kThreads) lds[e] = 0ull;
   __syncthreads();
 
   PushAcc acc{0.0, 0.0, 0.0};
 #pragma unroll 2
   for (int k = 0; k < kPPT; ++k) {
     const int i = base + k * kThreads + tid;
-    if (i < n) push_particle<R, RR, COMP>(a, sp, s, i, dc, acc);
+    push_particle<R, RR, COMP>(a, sp, s, i, cl[k], dc, acc);
   }
 
-  // used window range of the work-group
-  const int lo = wave_min(dc.jmin), hi = wave_max(dc.jmax);
-  if (lane == 0) {
-    atomicMin(&s_lo, lo);
-    atomicMax(&s_hi, hi);
-  }
   const double r0 = wave_sum(acc.rad), r1 = wave_sum(acc.esc), r2 = wave_sum(acc.stiff);
   if (lane == 0) {
     s_red[0][wid] = r0;
@@ -380,14 +396,19 @@ __device__ __forceinline__ void push_tile(const PushArgs<R>& a, int s, int tile,
   }
   __syncthreads();
 
-  // one global atomic per touched window node and component
-  const int wlo = s_lo, whi = s_hi;
-  if (wlo <= whi) {
-    const int ns = whi - wlo + 1;
-    for (int e = wid; e < 3 * ns; e += kThreads / kLanes) {
-      const int comp = e / ns, r = wlo + e % ns;
-      const long long v = wave_sum((long long)lds[((comp * kNW + r) << 6) + lane]);
-      if (lane == 0 && v != 0) atomicAdd(a.J[comp] + dc.wlo + r, (unsigned long long)v);
+  // one global atomic per window slot and component: each group of R lanes
+  // holds the R copies of one slot
+  if (dc.use_lds) {
+    const int Rm = (1 << sh) - 1;
+    for (int e0 = wid * kLanes; e0 < E; e0 += kThreads) {
+      const int e = e0 + lane;
+      long long v = e < E ? (long long)lds[e] : 0ll;
+      for (int o = 1; o <= Rm; o <<= 1) v += __shfl_xor(v, o);
+      if ((lane & Rm) == 0 && e < E && v != 0) {
+        const int slot = e >> sh;
+        const int comp = slot / dc.W, j = slot - comp * dc.W;
+        atomicAdd(a.J[comp] + dc.wlo + j, (unsigned long long)v);
+      }
     }
   }
   if (tid == 0) {
@@ -406,7 +427,7 @@ __device__ __forceinline__ void push_tile(const PushArgs<R>& a, int s, int tile,
 
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_push(PushArgs<R> a) {
-  __shared__ unsigned long long lds[3 * kNW * kLanes];
+  __shared__ unsigned long long lds[kLdsSlots];
   const int tile = blockIdx.x;
   const int s = tile < a.tiles0 ? 0 : 1;
   const int tl = s ? tile - a.tiles0 : tile;
@@ -598,8 +619,12 @@ struct SortArgs {
 };
 
 constexpr int kSortThreads = 256;
+constexpr int kSortPPT = 16;                       // particles per thread per sort tile
+constexpr int kSortTile = kSortThreads * kSortPPT;
+constexpr int kSortWin = 4096;                     // LDS cell window of a sort tile
 
-// wave-aggregated atomicAdd(ptr[key], 1) returning each lane's slot
+// wave-aggregated atomicAdd(ptr[key], 1) returning each lane's slot: one
+// atomic per distinct key in the wave (ptr may point to LDS or HBM)
 __device__ __forceinline__ int wave_claim(int* ptr, int key, bool valid) {
   const int lane = threadIdx.x & 63;
   unsigned long long active = __ballot(valid);
@@ -617,16 +642,60 @@ __device__ __forceinline__ int wave_claim(int* ptr, int key, bool valid) {
   return slot;
 }
 
+// Cell range of a sort tile (block-uniform result).
+__device__ __forceinline__ void tile_range(const int* cl, int& lo, int& hi, int* sm) {
+  int a = INT_MAX, b = INT_MIN;
+#pragma unroll
+  for (int k = 0; k < kSortPPT; ++k)
+    if (cl[k] != kDead) {
+      a = min(a, cl[k]);
+      b = max(b, cl[k]);
+    }
+  a = wave_min(a);
+  b = wave_max(b);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();  // earlier readers of sm (previous tile) are done
+  if (lane == 0) {
+    sm[wid] = a;
+    sm[4 + wid] = b;
+  }
+  __syncthreads();
+  lo = min(min(sm[0], sm[1]), min(sm[2], sm[3]));
+  hi = max(max(sm[4], sm[5]), max(sm[6], sm[7]));
+}
+
+// per-cell particle counts: LDS histogram over the tile's cell window,
+// then one global atomic per occupied cell and tile
 template <typename R>
 __global__ __launch_bounds__(kSortThreads) void k_sort_hist(SortArgs<R> p) {
+  __shared__ int cnt[kSortWin];
+  __shared__ int sm[8];
   const int s = blockIdx.x < p.blocks0 ? 0 : 1;
   const int b = s ? blockIdx.x - p.blocks0 : blockIdx.x;
-  const int nb = s ? gridDim.x - p.blocks0 : p.blocks0;
   const long long n = p.count[s];
-  for (long long i0 = (long long)b * kSortThreads; i0 < n; i0 += (long long)nb * kSortThreads) {
-    const long long i = i0 + threadIdx.x;
-    const int c = i < n ? p.src[s].cell[i] : kDead;
-    wave_claim(p.cnt[s], c, c != kDead);
+  const long long base = (long long)b * kSortTile;
+  if (base >= n) return;
+  int cl[kSortPPT];
+#pragma unroll
+  for (int k = 0; k < kSortPPT; ++k) {
+    const long long i = base + k * kSortThreads + threadIdx.x;
+    cl[k] = i < n ? p.src[s].cell[i] : kDead;
+  }
+  int lo, hi;
+  tile_range(cl, lo, hi, sm);
+  if (lo > hi) return;
+  const int W = hi - lo + 1;
+  if (W <= kSortWin) {
+    for (int e = threadIdx.x; e < W; e += kSortThreads) cnt[e] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kSortPPT; ++k) wave_claim(cnt, cl[k] - lo, cl[k] != kDead);
+    __syncthreads();
+    for (int e = threadIdx.x; e < W; e += kSortThreads)
+      if (cnt[e]) atomicAdd(p.cnt[s] + lo + e, cnt[e]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < kSortPPT; ++k) wave_claim(p.cnt[s], cl[k], cl[k] != kDead);
   }
 }
 
@@ -660,30 +729,61 @@ __global__ __launch_bounds__(1024) void k_sort_scan(int* cnt0, int* cnt1, int* c
   if (t == 1023) new_count[blockIdx.x] = part[1023];
 }
 
+// scatter to the destination arrays: each tile claims, per occupied cell,
+// one contiguous range of the cell's bucket with a single global atomic and
+// hands out positions inside it through an LDS counter
 template <typename R>
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortArgs<R> p) {
+  __shared__ int cnt[kSortWin];
+  __shared__ int sm[8];
   const int s = blockIdx.x < p.blocks0 ? 0 : 1;
   const int b = s ? blockIdx.x - p.blocks0 : blockIdx.x;
-  const int nb = s ? gridDim.x - p.blocks0 : p.blocks0;
   const long long n = p.count[s];
+  const long long base = (long long)b * kSortTile;
+  if (base >= n) return;
   const SpeciesDev<R> src = p.src[s], dst = p.dst[s];
   const bool comp = s == 0 && p.comp;
-  for (long long i0 = (long long)b * kSortThreads; i0 < n; i0 += (long long)nb * kSortThreads) {
-    const long long i = i0 + threadIdx.x;
-    const int c = i < n ? src.cell[i] : kDead;
-    const int j = wave_claim(p.cursor[s], c, c != kDead);
-    if (c != kDead) {
-      dst.cell[j] = c;
-      dst.off[j] = src.off[i];
-      dst.ux[j] = src.ux[i];
-      dst.uy[j] = src.uy[i];
-      dst.uz[j] = src.uz[i];
-      dst.w[j] = src.w[i];
-      if (comp) {
-        dst.rx[j] = src.rx[i];
-        dst.ry[j] = src.ry[i];
-        dst.rz[j] = src.rz[i];
-      }
+  int cl[kSortPPT], pos[kSortPPT];
+#pragma unroll
+  for (int k = 0; k < kSortPPT; ++k) {
+    const long long i = base + k * kSortThreads + threadIdx.x;
+    cl[k] = i < n ? src.cell[i] : kDead;
+  }
+  int lo, hi;
+  tile_range(cl, lo, hi, sm);
+  if (lo > hi) return;
+  const int W = hi - lo + 1;
+  if (W <= kSortWin) {
+    for (int e = threadIdx.x; e < W; e += kSortThreads) cnt[e] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kSortPPT; ++k) pos[k] = wave_claim(cnt, cl[k] - lo, cl[k] != kDead);
+    __syncthreads();
+    for (int e = threadIdx.x; e < W; e += kSortThreads)
+      cnt[e] = cnt[e] ? atomicAdd(p.cursor[s] + lo + e, cnt[e]) : 0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kSortPPT; ++k)
+      if (cl[k] != kDead) pos[k] += cnt[cl[k] - lo];
+  } else {
+#pragma unroll
+    for (int k = 0; k < kSortPPT; ++k) pos[k] = wave_claim(p.cursor[s], cl[k], cl[k] != kDead);
+  }
+#pragma unroll 4
+  for (int k = 0; k < kSortPPT; ++k) {
+    if (cl[k] == kDead) continue;
+    const long long i = base + k * kSortThreads + threadIdx.x;
+    const int j = pos[k];
+    dst.cell[j] = cl[k];
+    dst.off[j] = src.off[i];
+    dst.ux[j] = src.ux[i];
+    dst.uy[j] = src.uy[i];
+    dst.uz[j] = src.uz[i];
+    dst.w[j] = src.w[i];
+    if (comp) {
+      dst.rx[j] = src.rx[i];
+      dst.ry[j] = src.ry[i];
+      dst.rz[j] = src.rz[i];
     }
   }
 }
@@ -759,55 +859,87 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 
 __device__ __forceinline__ long long wave_sum_ll(long long v) { return wave_sum(v); }
 
+// Kinetic energy (FP64) and integer charge of the particles.  Each block
+// walks sort-sized tiles (blocks of a species stride over its tiles in a
+// fixed order); the charge of a tile is gathered in an LDS window and added
+// to HBM with one atomic per node.
 template <typename R>
 __global__ __launch_bounds__(kDiagThreads) void k_diag_particles(DiagArgs<R> p) {
+  static_assert(kDiagThreads == kSortThreads, "diag tiles reuse the sort tiling");
   __shared__ double sh[kDiagThreads / 64];
+  __shared__ long long sa[kDiagThreads / 64];
+  __shared__ unsigned long long rw[kSortWin + 1];
+  __shared__ int sm[8];
   const int s = blockIdx.x < kDiagPartBlocks ? 0 : 1;
   const int b = blockIdx.x - s * kDiagPartBlocks;
   const long long n = p.count[s];
   const SpeciesDev<R> sp = p.sp[s];
+  const int lane = threadIdx.x & 63;
   double ke = 0.0;
   long long alive = 0;
-  for (long long i0 = (long long)b * kDiagThreads; i0 < n;
-       i0 += (long long)kDiagPartBlocks * kDiagThreads) {
-    const long long i = i0 + threadIdx.x;
-    int c = kDead;
-    R o = R(0);
-    int qw = 0;
-    if (i < n) {
-      c = sp.cell[i];
-      if (c != kDead) {
+  for (long long base = (long long)b * kSortTile; base < n;
+       base += (long long)kDiagPartBlocks * kSortTile) {
+    int cl[kSortPPT];
+#pragma unroll
+    for (int k = 0; k < kSortPPT; ++k) {
+      const long long i = base + k * kSortThreads + threadIdx.x;
+      cl[k] = i < n ? sp.cell[i] : kDead;
+    }
+    int lo, hi;
+    tile_range(cl, lo, hi, sm);
+    if (lo > hi) continue;  // block-uniform
+    const int W = hi - lo + 2;  // nodes lo .. hi + 1
+    const bool win = W <= kSortWin + 1;
+    if (win) {
+      for (int e = threadIdx.x; e < W; e += kSortThreads) rw[e] = 0ull;
+      __syncthreads();
+    }
+#pragma unroll 4
+    for (int k = 0; k < kSortPPT; ++k) {
+      const long long i = base + k * kSortThreads + threadIdx.x;
+      const int c = cl[k];
+      const bool valid = c != kDead;
+      long long r0 = 0, r1 = 0;
+      if (valid) {
         const double ux = sp.ux[i], uy = sp.uy[i], uz = sp.uz[i];
         const double g = sqrt(1.0 + ux * ux + uy * uy + uz * uz);
         ke += (double)sp.w[i] * p.mass[s] * (g - 1.0);
-        o = sp.off[i];
-        qw = p.Z[s] * (int)rint(sp.w[i] * p.sw);
+        const int q = (int)(sp.off[i] * R(kTwo24));
+        const int qw = p.Z[s] * (int)rint(sp.w[i] * p.sw);
+        r0 = (long long)qw * (kTwo24 - q);
+        r1 = (long long)qw * q;
         alive += 1;
       }
-    }
-    // integer charge: wave-aggregate equal cells, then one atomic per cell
-    const bool valid = c != kDead;
-    const int q = valid ? (int)(o * R(kTwo24)) : 0;
-    const long long r0 = (long long)qw * (kTwo24 - q), r1 = (long long)qw * q;
-    const int lane = threadIdx.x & 63;
-    unsigned long long active = __ballot(valid);
-    while (active) {
-      const int leader = __ffsll((long long)active) - 1;
-      const int lc = __shfl(c, leader);
-      const bool mine = valid && c == lc && ((active >> lane) & 1ull);
-      const long long a0 = wave_sum(mine ? r0 : 0ll);
-      const long long a1 = wave_sum(mine ? r1 : 0ll);
-      if (lane == leader) {
-        atomicAdd((unsigned long long*)p.rho + lc + 1, (unsigned long long)a0);
-        atomicAdd((unsigned long long*)p.rho + lc + 2, (unsigned long long)a1);
+      // wave-aggregate equal cells, then one add per distinct cell
+      unsigned long long active = __ballot(valid);
+      while (active) {
+        const int leader = __ffsll((long long)active) - 1;
+        const int lc = __shfl(c, leader);
+        const bool mine = valid && c == lc && ((active >> lane) & 1ull);
+        const long long a0 = wave_sum(mine ? r0 : 0ll);
+        const long long a1 = wave_sum(mine ? r1 : 0ll);
+        if (lane == leader) {
+          if (win) {
+            atomicAdd(rw + (lc - lo), (unsigned long long)a0);
+            atomicAdd(rw + (lc - lo) + 1, (unsigned long long)a1);
+          } else {
+            atomicAdd((unsigned long long*)p.rho + lc + 1, (unsigned long long)a0);
+            atomicAdd((unsigned long long*)p.rho + lc + 2, (unsigned long long)a1);
+          }
+        }
+        active &= ~__ballot(mine);
       }
-      active &= ~__ballot(mine);
+    }
+    if (win) {
+      __syncthreads();
+      for (int e = threadIdx.x; e < W; e += kSortThreads)
+        if (rw[e]) atomicAdd((unsigned long long*)p.rho + lo + e + 1, rw[e]);
+      __syncthreads();
     }
   }
   const double t = block_sum(ke, sh);
   const long long na = wave_sum((long long)alive);
-  __shared__ long long sa[kDiagThreads / 64];
-  if ((threadIdx.x & 63) == 0) sa[threadIdx.x >> 6] = na;
+  if (lane == 0) sa[threadIdx.x >> 6] = na;
   __syncthreads();
   if (threadIdx.x == 0) {
     long long tot = 0;
@@ -868,29 +1000,46 @@ struct DiagOutDev {
   long long gauss_int, alive0, alive1;
 };
 
-__global__ void k_diag_final(const double* part, const long long* ipart, const double* acc,
-                             int tiles, DiagOutDev* out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  DiagOutDev o{};
-  for (int b = 0; b < kDiagPartBlocks; ++b) {
-    o.K_e += part[b];
-    o.K_i += part[kDiagPartBlocks + b];
-    o.alive0 += ipart[kDiagFieldBlocks + b];
-    o.alive1 += ipart[kDiagFieldBlocks + kDiagPartBlocks + b];
+// fixed-order parallel reduction: thread t sums entries t, t + 256, ...,
+// then a fixed tree over threads
+__device__ __forceinline__ double fixed_sum(const double* x, int n, int stride, int off,
+                                            double* sh) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) v += x[(size_t)i * stride + off];
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
   }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(256) void k_diag_final(const double* part, const long long* ipart,
+                                                    const double* acc, int tiles,
+                                                    DiagOutDev* out) {
+  __shared__ double sh[256];
   const int base = 2 * kDiagPartBlocks;
-  for (int b = 0; b < kDiagFieldBlocks; ++b) {
-    o.U_Ex += part[base + b];
-    o.U_Et += part[base + kDiagFieldBlocks + b];
-    o.U_B += part[base + 2 * kDiagFieldBlocks + b];
-    o.gauss_int = ipart[b] > o.gauss_int ? ipart[b] : o.gauss_int;
+  DiagOutDev o{};
+  o.K_e = fixed_sum(part, kDiagPartBlocks, 1, 0, sh);
+  o.K_i = fixed_sum(part + kDiagPartBlocks, kDiagPartBlocks, 1, 0, sh);
+  o.U_Ex = fixed_sum(part + base, kDiagFieldBlocks, 1, 0, sh);
+  o.U_Et = fixed_sum(part + base + kDiagFieldBlocks, kDiagFieldBlocks, 1, 0, sh);
+  o.U_B = fixed_sum(part + base + 2 * kDiagFieldBlocks, kDiagFieldBlocks, 1, 0, sh);
+  o.E_rad = fixed_sum(acc, tiles, 4, 0, sh);
+  o.E_esc = fixed_sum(acc, tiles, 4, 1, sh) + fixed_sum(acc, tiles, 4, 2, sh);
+  o.n_stiff = fixed_sum(acc, tiles, 4, 3, sh);
+  if (threadIdx.x == 0) {
+    for (int b = 0; b < kDiagPartBlocks; ++b) {
+      o.alive0 += ipart[kDiagFieldBlocks + b];
+      o.alive1 += ipart[kDiagFieldBlocks + kDiagPartBlocks + b];
+    }
+    for (int b = 0; b < kDiagFieldBlocks; ++b)
+      o.gauss_int = ipart[b] > o.gauss_int ? ipart[b] : o.gauss_int;
+    *out = o;
   }
-  for (int t = 0; t < tiles; ++t) {
-    o.E_rad += acc[4 * t];
-    o.E_esc += acc[4 * t + 1] + acc[4 * t + 2];
-    o.n_stiff += acc[4 * t + 3];
-  }
-  *out = o;
 }
 
 // ---------------------------------------------------------------- spectrum

@@ -331,7 +331,7 @@ pic_status launch_sort(pic_run* r, hipStream_t st) {
   p.nx = d.nx;
   p.comp = (r->cfg.rr && r->cfg.rr_compensated && r->cfg.precision == PIC_FP32) ? 1 : 0;
   auto blocks = [](long long n) {
-    return (int)std::min<long long>(4096, std::max<long long>(1, (n + kSortThreads - 1) / kSortThreads));
+    return (int)std::max<long long>(1, (n + kSortTile - 1) / kSortTile);
   };
   p.blocks0 = blocks(r->n_max[0]);
   const int grid = p.blocks0 + blocks(r->n_max[1]);
@@ -400,7 +400,7 @@ pic_status do_diag(pic_run* r, pic_diag_out* out, hipStream_t st) {
   HIP_TRY(hipMemsetAsync(r->rho, 0, sizeof(long long) * (d.nx + 3), st));
   hipLaunchKernelGGL(k_diag_particles<R>, dim3(2 * kDiagPartBlocks), dim3(kDiagThreads), 0, st, p);
   hipLaunchKernelGGL(k_diag_fields<R>, dim3(kDiagFieldBlocks), dim3(kDiagThreads), 0, st, p);
-  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, st, r->part, r->ipart, r->acc,
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, st, r->part, r->ipart, r->acc,
                      r->tiles_max, r->dout);
   HIP_TRY(hipGetLastError());
   DiagOutDev o;
@@ -530,7 +530,7 @@ pic_status pic_get_info(const pic_run* r, pic_info* o) {
   o->n_init[1] = r->n_max[1];
   o->step = r->step;
   o->tile = kTile;
-  o->window = kNW;
+  o->lds_slots = kLdsSlots;
   return PIC_OK;
 }
 

@@ -100,7 +100,7 @@ class Run:
         N.check(self.lib.pic_get_info(self._h, C.byref(o)), "pic_get_info")
         return dict(n_cells=o.n_cells, precision=o.precision, dx=o.dx, dt=o.dt, eps_rr=o.eps_rr,
                     w_ref=o.w_ref, capacity=o.capacity, n_init=(o.n_init[0], o.n_init[1]),
-                    step=o.step, tile=o.tile, window=o.window)
+                    step=o.step, tile=o.tile, lds_slots=o.lds_slots)
 
     def diag(self, allow_nonfinite: bool = False) -> dict:
         o = N.PicDiagOut()

@@ -85,16 +85,20 @@ def test_quiet_start_matches_oracle():
 
 
 # --------------------------------------------------------------------------- move + deposit
-@pytest.mark.parametrize("n_e,n_i", [(3000, 700), (40000, 9000)])
-def test_move_and_deposit_bit_exact_without_fields(n_e, n_i):
+@pytest.mark.parametrize("n_e,n_i,box,ordered", [
+    (3000, 700, 4.0, True),      # wide tiles: few private LDS copies per node
+    (40000, 9000, 4.0, True),    # dense tiles: one LDS copy per lane
+    (2500, 900, 20.0, False),    # tiles spanning > 1020 cells: global atomics
+])
+def test_move_and_deposit_bit_exact_without_fields(n_e, n_i, box, ordered):
     # E = B = 0: the push leaves u unchanged bit for bit, so cell, offset and
     # the integer currents must equal the contract evaluated on the inputs
-    cfg = preset("c1", box_lambda=4.0, x_foil=1.0)
+    cfg = preset("c1", box_lambda=box, x_foil=1.0)
     sim = _oracle_for(cfg)
     n = sim.nx
     run = _run(cfg, capacity=max(n_e, n_i))
-    pe = random_particles(10 + n_e, n_e, 2, n - 2, sim.w_ref, u_lo=1e-3, u_hi=1e3)
-    pi = random_particles(11 + n_e, n_i, 2, n - 2, sim.w_ref, u_lo=1e-3, u_hi=1e2)
+    pe = random_particles(10 + n_e, n_e, 2, n - 2, sim.w_ref, u_lo=1e-3, u_hi=1e3, sort=ordered)
+    pi = random_particles(11 + n_e, n_i, 2, n - 2, sim.w_ref, u_lo=1e-3, u_hi=1e2, sort=ordered)
     run.set_state({0: pe, 1: pi}, fields=_zero_fields(n), step=0)
     run.push_deposit()
     st = run.get_state()
