@@ -9,7 +9,8 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpic.so")
+# PIC_LIB may name another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("PIC_LIB") or os.path.join(HERE, "libpic.so")
 
 PIC_OK, PIC_EINVAL, PIC_ENOMEM, PIC_EHIP, PIC_ENONFINITE, PIC_EBUSY = 0, -1, -2, -3, -4, -5
 PIC_FP32, PIC_FP64 = 0, 1

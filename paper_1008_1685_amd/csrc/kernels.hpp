@@ -24,11 +24,25 @@
 
 namespace pic {
 
+#ifndef PIC_PUSH_PPT
+#define PIC_PUSH_PPT 16
+#endif
+#ifndef PIC_PUSH_LDS_SLOTS
+#define PIC_PUSH_LDS_SLOTS 3072
+#endif
+#ifndef PIC_PUSH_UNROLL
+#define PIC_PUSH_UNROLL 2
+#endif
+#ifndef PIC_PUSH_PREFETCH
+#define PIC_PUSH_PREFETCH 1
+#endif
+
 constexpr int kDead = INT_MIN;        // cell index of a removed particle
 constexpr int kThreads = 256;         // push work-group
-constexpr int kPPT = 8;               // particles per thread per tile
+constexpr int kPPT = PIC_PUSH_PPT;    // particles per thread per tile
 constexpr int kTile = kThreads * kPPT;
-constexpr int kLdsSlots = 3072;       // 64-bit LDS current accumulators per work-group (24 KB)
+constexpr int kLdsSlots = PIC_PUSH_LDS_SLOTS;  // 64-bit LDS current accumulators per work-group
+constexpr int kUnroll = PIC_PUSH_UNROLL;      // push loop unroll
 constexpr int kLanes = 64;            // wavefront width
 constexpr int kFieldChunk = 256;      // nodes per field work-group
 constexpr int kTwo24 = 1 << 24;
@@ -46,13 +60,22 @@ struct SpeciesDev {
   float* rz;
 };
 
+// Grid fields, interleaved so that one particle gathers with four loads:
+//   N[i] = (E_y, E_z) at node i = 0..n,
+//   H[h] = (E_x, B_y, B_z, 0) at half-node h = 0..n+1 (x = (h - 1/2) dx).
+template <typename R>
+struct alignas(2 * sizeof(R)) NodeF {
+  R ey, ez;
+};
+template <typename R>
+struct alignas(16) HalfF {
+  R ex, by, bz, pad;
+};
+
 template <typename R>
 struct FieldsDev {
-  R* Ex;  // half-nodes 0..n+1
-  R* Ey;  // nodes 0..n
-  R* Ez;
-  R* By;  // half-nodes
-  R* Bz;
+  NodeF<R>* N;
+  HalfF<R>* H;
 };
 
 template <typename R>
@@ -74,11 +97,32 @@ struct PushArgs {
   int rr0;                       // RR on species 0 (electrons)
   int comp;                      // compensated RR accumulation (fp32 only)
   R sw;                          // 256 / w_ref (charge-weight scale)
+  int qw_ref[2];                 // charge weight of a particle of weight w_ref
 };
 
 // ---------------------------------------------------------------- helpers
+// Approximate (about 1 ulp) reciprocal, reciprocal square root and square
+// root for the Boris and RR arithmetic; the contract lines use IEEE ops.
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
+
+// Element i of an array at a wave-uniform base: a 32-bit byte offset added
+// to the 64-bit base lets the compiler use scalar-base addressing instead of
+// per-lane 64-bit address arithmetic.  Arrays stay below 4 GiB (capacity
+// limits in the host code).
+template <typename T>
+__device__ __forceinline__ T ld(const T* p, unsigned i) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) +
+                                     (size_t)(i * (unsigned)sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ void st(T* p, unsigned i, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(p) + (size_t)(i * (unsigned)sizeof(T))) = v;
+}
 
 __device__ __forceinline__ long long wave_sum(long long v) {
 #pragma unroll
@@ -138,12 +182,13 @@ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
 // the copy), so lanes of a wave that hit the same node add to different
 // words.  Tiles whose window does not fit use global atomics instead.
 struct DepositCtx {
-  unsigned long long* lds;  // [3][W][R]
+  unsigned long long* lds;  // [3][W][R], current / qw_ref of particles with qw == qw_ref
   unsigned long long* J[3];
   int wlo;
   int W;
   int rshift;
   int copy;
+  int qw_ref;
   bool use_lds;
 };
 
@@ -164,80 +209,107 @@ __device__ __forceinline__ void deposit(DepositCtx& d, int c, R o, int c1, R o1,
   const int wn2 = d1 ? q1 : 0;
   const int F0 = wo0 - wn0;
   const int F1 = F0 + wo1 - wn1;
-  const long long vy24 = (long long)rint(vy * R(kTwo24));
-  const long long vz24 = (long long)rint(vz * R(kTwo24));
-  const long long jx0 = (long long)qw * F0;
-  const long long jy0 = (long long)qw * ((vy24 * (wo0 + wn0)) >> 25);
-  const long long jy1 = (long long)qw * ((vy24 * (wo1 + wn1)) >> 25);
-  const long long jz0 = (long long)qw * ((vz24 * (wo0 + wn0)) >> 25);
-  const long long jz1 = (long long)qw * ((vz24 * (wo1 + wn1)) >> 25);
+  const int vy24 = (int)rint(vy * R(kTwo24));  // |v| < 1: |vy24| <= 2^24
+  const int vz24 = (int)rint(vz * R(kTwo24));
+  // unweighted Jy, Jz terms: floor(v24 (Wo + Wn) / 2^25), |term| <= 2^24
+  const int ty0 = (int)(((long long)vy24 * (wo0 + wn0)) >> 25);
+  const int ty1 = (int)(((long long)vy24 * (wo1 + wn1)) >> 25);
+  const int ty2 = (int)(((long long)vy24 * (wo2 + wn2)) >> 25);
+  const int tz0 = (int)(((long long)vz24 * (wo0 + wn0)) >> 25);
+  const int tz1 = (int)(((long long)vz24 * (wo1 + wn1)) >> 25);
+  const int tz2 = (int)(((long long)vz24 * (wo2 + wn2)) >> 25);
   const bool moved = (c1 != c);
   const int j0 = base + 1;  // Jx half-node base+1/2 and Jy node base share index base+1
-  if (d.use_lds) {
+  if (d.use_lds && qw == d.qw_ref) {
+    // LDS holds sums of unweighted terms; the flush multiplies by qw_ref
     const int r = j0 - d.wlo;  // 0 <= r <= W - 3 by construction of the window
-    unsigned long long* L = d.lds + d.copy;
-    const int W = d.W, sh = d.rshift;
-    atomicAdd(L + ((0 * W + r) << sh), (unsigned long long)jx0);
-    atomicAdd(L + ((1 * W + r) << sh), (unsigned long long)jy0);
-    atomicAdd(L + ((1 * W + r + 1) << sh), (unsigned long long)jy1);
-    atomicAdd(L + ((2 * W + r) << sh), (unsigned long long)jz0);
-    atomicAdd(L + ((2 * W + r + 1) << sh), (unsigned long long)jz1);
+    // slot (comp, r + k) of this lane's copy: x0 + comp * cs + k * ss
+    const int ss = 1 << d.rshift, cs = d.W << d.rshift;
+    unsigned long long* x0 = d.lds + d.copy + (r << d.rshift);
+    unsigned long long* y0 = x0 + cs;
+    unsigned long long* z0 = y0 + cs;
+    atomicAdd(x0, (unsigned long long)(long long)F0);
+    atomicAdd(y0, (unsigned long long)(long long)ty0);
+    atomicAdd(y0 + ss, (unsigned long long)(long long)ty1);
+    atomicAdd(z0, (unsigned long long)(long long)tz0);
+    atomicAdd(z0 + ss, (unsigned long long)(long long)tz1);
     if (moved) {
-      const long long jx1 = (long long)qw * F1;
-      const long long jy2 = (long long)qw * ((vy24 * (wo2 + wn2)) >> 25);
-      const long long jz2 = (long long)qw * ((vz24 * (wo2 + wn2)) >> 25);
-      atomicAdd(L + ((0 * W + r + 1) << sh), (unsigned long long)jx1);
-      atomicAdd(L + ((1 * W + r + 2) << sh), (unsigned long long)jy2);
-      atomicAdd(L + ((2 * W + r + 2) << sh), (unsigned long long)jz2);
+      atomicAdd(x0 + ss, (unsigned long long)(long long)F1);
+      atomicAdd(y0 + 2 * ss, (unsigned long long)(long long)ty2);
+      atomicAdd(z0 + 2 * ss, (unsigned long long)(long long)tz2);
     }
   } else {
-    atomicAdd(d.J[0] + j0, (unsigned long long)jx0);
-    atomicAdd(d.J[1] + j0, (unsigned long long)jy0);
-    atomicAdd(d.J[1] + j0 + 1, (unsigned long long)jy1);
-    atomicAdd(d.J[2] + j0, (unsigned long long)jz0);
-    atomicAdd(d.J[2] + j0 + 1, (unsigned long long)jz1);
+    const long long q = qw;
+    atomicAdd(d.J[0] + j0, (unsigned long long)(q * F0));
+    atomicAdd(d.J[1] + j0, (unsigned long long)(q * ty0));
+    atomicAdd(d.J[1] + j0 + 1, (unsigned long long)(q * ty1));
+    atomicAdd(d.J[2] + j0, (unsigned long long)(q * tz0));
+    atomicAdd(d.J[2] + j0 + 1, (unsigned long long)(q * tz1));
     if (moved) {
-      const long long jx1 = (long long)qw * F1;
-      const long long jy2 = (long long)qw * ((vy24 * (wo2 + wn2)) >> 25);
-      const long long jz2 = (long long)qw * ((vz24 * (wo2 + wn2)) >> 25);
-      atomicAdd(d.J[0] + j0 + 1, (unsigned long long)jx1);
-      atomicAdd(d.J[1] + j0 + 2, (unsigned long long)jy2);
-      atomicAdd(d.J[2] + j0 + 2, (unsigned long long)jz2);
+      atomicAdd(d.J[0] + j0 + 1, (unsigned long long)(q * F1));
+      atomicAdd(d.J[1] + j0 + 2, (unsigned long long)(q * ty2));
+      atomicAdd(d.J[2] + j0 + 2, (unsigned long long)(q * tz2));
     }
   }
 }
 
+// per-thread partial sums (a thread pushes kPPT particles; FP64 from the
+// work-group sum on)
 struct PushAcc {
-  double rad, esc, stiff;
+  float rad, esc, stiff;
 };
+
+// Stored state of one particle (besides its cell).
+template <typename R>
+struct PData {
+  R o, ux, uy, uz, w;
+  float rx, ry, rz;
+};
+
+template <typename R, bool COMP>
+__device__ __forceinline__ PData<R> load_particle(const SpeciesDev<R>& sp, int i, int c) {
+  PData<R> d{};
+  if (c != kDead) {
+    const unsigned ui = (unsigned)i;
+    d.o = ld(sp.off, ui);
+    d.ux = ld(sp.ux, ui);
+    d.uy = ld(sp.uy, ui);
+    d.uz = ld(sp.uz, ui);
+    d.w = ld(sp.w, ui);
+    if (COMP) {
+      d.rx = ld(sp.rx, ui);
+      d.ry = ld(sp.ry, ui);
+      d.rz = ld(sp.rz, ui);
+    }
+  }
+  return d;
+}
 
 // One particle: gather, Boris, RR, move, deposit, store.
 template <typename R, bool RR, bool COMP>
 __device__ __forceinline__ void push_particle(const PushArgs<R>& a, const SpeciesDev<R>& sp,
-                                              int s, int i, int c, DepositCtx& dc, PushAcc& acc) {
+                                              int s, int i, int c, const PData<R>& pd,
+                                              DepositCtx& dc, PushAcc& acc) {
   if (c == kDead) return;
-  const R o = sp.off[i];
-  const R ux = sp.ux[i], uy = sp.uy[i], uz = sp.uz[i];
-  const R w = sp.w[i];
-  float rx = 0.f, ry = 0.f, rz = 0.f;
-  if (COMP) {
-    rx = sp.rx[i];
-    ry = sp.ry[i];
-    rz = sp.rz[i];
-  }
+  const unsigned ui = (unsigned)i;
+  const R o = pd.o, ux = pd.ux, uy = pd.uy, uz = pd.uz, w = pd.w;
+  float rx = pd.rx, ry = pd.ry, rz = pd.rz;
 
   // ---- gather E^n, B^n (linear weights; E_y,E_z on nodes, the rest on half-nodes)
+  const unsigned uc = (unsigned)c;
   const R on = R(1) - o;
-  const R ey = on * a.f.Ey[c] + o * a.f.Ey[c + 1];
-  const R ez = on * a.f.Ez[c] + o * a.f.Ez[c + 1];
+  const NodeF<R> n0 = ld(a.f.N, uc), n1 = ld(a.f.N, uc + 1);
+  const R ey = on * n0.ey + o * n1.ey;
+  const R ez = on * n0.ez + o * n1.ez;
   const R sx = o + R(0.5);
-  const int hb = sx >= R(1);
+  const unsigned hb = sx >= R(1);
   const R fh = hb ? sx - R(1) : sx;
-  const int h = c + hb;
+  const unsigned h = uc + hb;
   const R fn = R(1) - fh;
-  const R ex = fn * a.f.Ex[h] + fh * a.f.Ex[h + 1];
-  const R by = fn * a.f.By[h] + fh * a.f.By[h + 1];
-  const R bz = fn * a.f.Bz[h] + fh * a.f.Bz[h + 1];
+  const HalfF<R> h0 = ld(a.f.H, h), h1 = ld(a.f.H, h + 1);
+  const R ex = fn * h0.ex + fh * h1.ex;
+  const R by = fn * h0.by + fh * h1.by;
+  const R bz = fn * h0.bz + fh * h1.bz;
 
   // ---- Boris (B_x = 0 in 1D)
   const R qh = a.qh[s];
@@ -245,7 +317,7 @@ __device__ __forceinline__ void push_particle(const PushArgs<R>& a, const Specie
   const R mx = ux + hx, my = uy + hy, mz = uz + hz;
   const R igm = rsq(R(1) + mx * mx + my * my + mz * mz);
   const R ty = qh * by * igm, tz = qh * bz * igm;
-  const R sf = R(2) / (R(1) + ty * ty + tz * tz);
+  const R sf = R(2) * rcp(R(1) + ty * ty + tz * tz);
   const R px = mx + (my * tz - mz * ty);
   const R py = my - mx * tz;
   const R pz = mz + mx * ty;
@@ -275,7 +347,7 @@ __device__ __forceinline__ void push_particle(const PushArgs<R>& a, const Specie
     ddx = k * ((Fy * bz - Fz * by) + vE * ex - g2b * vx);
     ddy = k * (vE * ey - Fx * bz - g2b * vy);
     ddz = k * (Fx * by + vE * ez - g2b * vz);
-    if (ddx * ddx + ddy * ddy + ddz * ddz > R(0.01) * (Lx * Lx + Ly * Ly + Lz * Lz)) acc.stiff += 1.0;
+    if (ddx * ddx + ddy * ddy + ddz * ddz > R(0.01) * (Lx * Lx + Ly * Ly + Lz * Lz)) acc.stiff += 1.f;
     if (COMP) {
       // increment plus the residual carried from earlier steps, added by TwoSum;
       // the new rounding residual is carried to the next step
@@ -295,14 +367,14 @@ __device__ __forceinline__ void push_particle(const PushArgs<R>& a, const Specie
       ny = Ly + ddy;
       nz = Lz + ddz;
     }
-    gL = sqrt(R(1) + Lx * Lx + Ly * Ly + Lz * Lz);
+    gL = fsqrt(R(1) + Lx * Lx + Ly * Ly + Lz * Lz);
   }
 
   // ---- move (contract arithmetic)
   R g, vy, vz, o1, shift;
   contract_move<R>(nx, ny, nz, o, a.cfl, g, vy, vz, o1, shift);
   if (!(fabs(shift) < R(4)) || !(g < R(1e30))) {  // NaN/Inf momentum: drop it, raise the flag
-    sp.cell[i] = kDead;
+    st(sp.cell, ui, kDead);
     atomicOr(a.flags, 1);
     return;
   }
@@ -313,22 +385,22 @@ __device__ __forceinline__ void push_particle(const PushArgs<R>& a, const Specie
   if (RR) {
     // gamma_L - gamma_new = -(d . (2 u_L + d)) / (gamma_L + gamma_new)
     const R num = ddx * (R(2) * Lx + ddx) + ddy * (R(2) * Ly + ddy) + ddz * (R(2) * Lz + ddz);
-    acc.rad += -(double)w * (double)num / ((double)gL + (double)g);
+    acc.rad -= (float)(w * num * rcp(gL + g));
   }
   if (c1 < 0 || c1 >= a.nx) {
-    sp.cell[i] = kDead;
-    acc.esc += (double)w * a.mass[s] * ((double)g - 1.0);
+    st(sp.cell, ui, kDead);
+    acc.esc += (float)(w * (R)a.mass[s] * (g - R(1)));
   } else {
-    sp.cell[i] = c1;
-    sp.off[i] = o1;
+    st(sp.cell, ui, c1);
+    st(sp.off, ui, o1);
   }
-  sp.ux[i] = nx;
-  sp.uy[i] = ny;
-  sp.uz[i] = nz;
+  st(sp.ux, ui, nx);
+  st(sp.uy, ui, ny);
+  st(sp.uz, ui, nz);
   if (COMP) {
-    sp.rx[i] = rx;
-    sp.ry[i] = ry;
-    sp.rz[i] = rz;
+    st(sp.rx, ui, rx);
+    st(sp.ry, ui, ry);
+    st(sp.rz, ui, rz);
   }
 }
 
@@ -346,12 +418,16 @@ __device__ __forceinline__ void push_tile(const PushArgs<R>& a, int s, int tile,
 #pragma unroll
   for (int k = 0; k < kPPT; ++k) {
     const int i = base + k * kThreads + tid;
-    cl[k] = i < n ? sp.cell[i] : kDead;
+    cl[k] = i < n ? ld(sp.cell, (unsigned)i) : kDead;
     if (cl[k] != kDead) {
       cmin = min(cmin, cl[k]);
       cmax = max(cmax, cl[k]);
     }
   }
+#if PIC_PUSH_PREFETCH
+  // first particle's loads overlap the window set-up below
+  PData<R> cur = load_particle<R, COMP>(sp, base + tid, cl[0]);
+#endif
   cmin = wave_min(cmin);
   cmax = wave_max(cmax);
   if (lane == 0) {
@@ -371,6 +447,7 @@ __device__ __forceinline__ void push_tile(const PushArgs<R>& a, int s, int tile,
   dc.J[2] = a.J[2];
   dc.wlo = cmin;
   dc.W = cmax - cmin + 4;
+  dc.qw_ref = a.qw_ref[s];
   int sh = 6;
   while (sh > 0 && 3 * dc.W * (1 << sh) > kLdsSlots) --sh;
   dc.rshift = sh;
@@ -381,14 +458,28 @@ __device__ __forceinline__ void push_tile(const PushArgs<R>& a, int s, int tile,
     for (int e = tid; e < E; e += kThreads) lds[e] = 0ull;
   __syncthreads();
 
-  PushAcc acc{0.0, 0.0, 0.0};
-#pragma unroll 2
+  PushAcc acc{0.f, 0.f, 0.f};
+#if PIC_PUSH_PREFETCH
+  // the next particle's loads are in flight while this one is computed
+#pragma unroll kUnroll
   for (int k = 0; k < kPPT; ++k) {
     const int i = base + k * kThreads + tid;
-    push_particle<R, RR, COMP>(a, sp, s, i, cl[k], dc, acc);
+    PData<R> nxt{};
+    if (k + 1 < kPPT) nxt = load_particle<R, COMP>(sp, i + kThreads, cl[k + 1]);
+    push_particle<R, RR, COMP>(a, sp, s, i, cl[k], cur, dc, acc);
+    cur = nxt;
   }
+#else
+#pragma unroll kUnroll
+  for (int k = 0; k < kPPT; ++k) {
+    const int i = base + k * kThreads + tid;
+    const PData<R> pd = load_particle<R, COMP>(sp, i, cl[k]);
+    push_particle<R, RR, COMP>(a, sp, s, i, cl[k], pd, dc, acc);
+  }
+#endif
 
-  const double r0 = wave_sum(acc.rad), r1 = wave_sum(acc.esc), r2 = wave_sum(acc.stiff);
+  const double r0 = wave_sum((double)acc.rad), r1 = wave_sum((double)acc.esc),
+               r2 = wave_sum((double)acc.stiff);
   if (lane == 0) {
     s_red[0][wid] = r0;
     s_red[1][wid] = r1;
@@ -407,7 +498,7 @@ __device__ __forceinline__ void push_tile(const PushArgs<R>& a, int s, int tile,
       if ((lane & Rm) == 0 && e < E && v != 0) {
         const int slot = e >> sh;
         const int comp = slot / dc.W, j = slot - comp * dc.W;
-        atomicAdd(a.J[comp] + dc.wlo + j, (unsigned long long)v);
+        atomicAdd(a.J[comp] + dc.wlo + j, (unsigned long long)(v * (long long)dc.qw_ref));
       }
     }
   }
@@ -494,14 +585,16 @@ __global__ __launch_bounds__(kFieldChunk) void k_field(FieldArgs<R> p) {
   for (int k = t; k < CH + 3; k += CH) {
     const int i = i0 - 2 + k;
     const bool ok = i >= 0 && i <= n;
-    sEy[k] = ok ? p.in.Ey[i] : R(0);
-    sEz[k] = ok ? p.in.Ez[i] : R(0);
+    const NodeF<R> v = ok ? p.in.N[i] : NodeF<R>{R(0), R(0)};
+    sEy[k] = v.ey;
+    sEz[k] = v.ez;
   }
   for (int k = t; k < CH + 2; k += CH) {
     const int h = i0 - 1 + k;
     const bool ok = h >= 0 && h <= n + 1;
-    sBy[k] = ok ? p.in.By[h] : R(0);
-    sBz[k] = ok ? p.in.Bz[h] : R(0);
+    const HalfF<R> v = ok ? p.in.H[h] : HalfF<R>{R(0), R(0), R(0), R(0)};
+    sBy[k] = v.by;
+    sBz[k] = v.bz;
   }
   for (int k = t; k < CH + 1; k += CH) {
     const int i = i0 - 1 + k;
@@ -580,8 +673,7 @@ __global__ __launch_bounds__(kFieldChunk) void k_field(FieldArgs<R> p) {
   // own outputs: node i = i0 + t, half-node h = i0 + t
   const int i = i0 + t;
   if (i <= n) {
-    p.out.Ey[i] = nEy[t + 1];
-    p.out.Ez[i] = nEz[t + 1];
+    p.out.N[i] = NodeF<R>{nEy[t + 1], nEz[t + 1]};
   }
   const int h = i0 + t;
   if (h <= n + 1) {
@@ -593,11 +685,9 @@ __global__ __launch_bounds__(kFieldChunk) void k_field(FieldArgs<R> p) {
       bz = sBz[t + 1];
       byv = sBy[t + 1];
     }
-    p.out.Bz[h] = bz;
-    p.out.By[h] = byv;
     const long long ex = p.Ex_int[h] - p.J[0][h];
     p.Ex_int[h] = ex;
-    p.out.Ex[h] = (R)((double)ex * p.sEx);
+    p.out.H[h] = HalfF<R>{(R)((double)ex * p.sEx), byv, bz, R(0)};
     p.Jnext[0][h] = 0ull;
   }
   if (i0 + t <= n + 2) {
@@ -959,10 +1049,12 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag_fields(DiagArgs<R> p) {
   for (int i = blockIdx.x * kDiagThreads + threadIdx.x; i <= n;
        i += kDiagFieldBlocks * kDiagThreads) {
     const double wn = (i == 0 || i == n) ? 0.5 : 1.0;
-    const double ey = p.f.Ey[i], ez = p.f.Ez[i];
+    const NodeF<R> nv = p.f.N[i];
+    const double ey = nv.ey, ez = nv.ez;
     ue += wn * (ey * ey + ez * ez);
     if (i >= 1) {  // half-node h = i covers cell i-1
-      const double ex = p.f.Ex[i], by = p.f.By[i], bz = p.f.Bz[i];
+      const HalfF<R> hv = p.f.H[i];
+      const double ex = hv.ex, by = hv.by, bz = hv.bz;
       ux += ex * ex;
       ub += by * by + bz * bz;
     }

@@ -87,8 +87,10 @@ pic_status derive(const pic_config* c, Derived* d) {
   d->w_ref = c->n0 * d->dx / c->ppc;
   d->n_foil = (long long)d->nf * c->ppc;
   d->cap = std::max<long long>(d->n_foil, c->capacity);
-  if (d->cap < 0 || d->cap > (1ll << 31) - kTile)
-    return fail(PIC_EINVAL, "capacity per species must be < 2^31");
+  // kernels address particle arrays with 32-bit byte offsets
+  const long long elem = c->precision == PIC_FP32 ? 4 : 8;
+  if (d->cap < 0 || d->cap * elem > (1ll << 32) - (long long)kTile * elem)
+    return fail(PIC_EINVAL, "capacity per species too large (arrays must stay below 4 GiB)");
   d->prec = c->precision;
   d->rsize = c->precision == PIC_FP32 ? sizeof(float) : sizeof(double);
   return PIC_OK;
@@ -122,7 +124,8 @@ struct pic_run {
   int pp;               // particle buffer (and count slot) parity
   // device memory carved from the workspace
   SpeciesBuf sp[2][2];  // [species][parity]
-  void* F[2][5];        // [parity][Ex, Ey, Ez, By, Bz]
+  void* FN[2];          // [parity] node fields (E_y, E_z)
+  void* FH[2];          // [parity] half-node fields (E_x, B_y, B_z, 0)
   unsigned long long* J[2][3];
   long long* Ex_int;
   long long* count;     // [parity][species]
@@ -170,8 +173,10 @@ void carve(pic_run* r, Carver& cv) {
         b.rz = cv.take<float>(d.cap);
       }
     }
-  for (int p = 0; p < 2; ++p)
-    for (int k = 0; k < 5; ++k) r->F[p][k] = cv.take<char>((size_t)(d.nx + 2) * rs);
+  for (int p = 0; p < 2; ++p) {
+    r->FN[p] = cv.take<char>((size_t)(d.nx + 1) * 2 * rs);
+    r->FH[p] = cv.take<char>((size_t)(d.nx + 2) * 4 * rs);
+  }
   for (int p = 0; p < 2; ++p)
     for (int k = 0; k < 3; ++k) r->J[p][k] = cv.take<unsigned long long>(d.nx + 3);
   r->Ex_int = cv.take<long long>(d.nx + 2);
@@ -198,8 +203,8 @@ SpeciesDev<R> dev(const SpeciesBuf& b) {
 }
 
 template <typename R>
-FieldsDev<R> fdev(void* const* F) {
-  return FieldsDev<R>{(R*)F[0], (R*)F[1], (R*)F[2], (R*)F[3], (R*)F[4]};
+FieldsDev<R> fdev(const pic_run* r, int parity) {
+  return FieldsDev<R>{(NodeF<R>*)r->FN[parity], (HalfF<R>*)r->FH[parity]};
 }
 
 __global__ void k_set_counts(long long* dst, long long a, long long b) {
@@ -252,7 +257,7 @@ pic_status launch_push(pic_run* r, hipStream_t st) {
   for (int s = 0; s < 2; ++s) a.sp[s] = dev<R>(r->sp[s][r->pp]);
   a.count = r->count + 2 * r->pp;
   a.tiles0 = t0;
-  a.f = fdev<R>(r->F[r->step & 1]);
+  a.f = fdev<R>(r, (int)(r->step & 1));
   for (int k = 0; k < 3; ++k) a.J[k] = r->J[r->step & 1][k];
   a.acc = r->acc;
   a.flags = r->flags;
@@ -269,6 +274,8 @@ pic_status launch_push(pic_run* r, hipStream_t st) {
   a.rr0 = r->cfg.rr != 0;
   a.comp = (r->cfg.rr && r->cfg.rr_compensated && r->cfg.precision == PIC_FP32) ? 1 : 0;
   a.sw = (R)(256.0 / d.w_ref);
+  for (int s = 0; s < 2; ++s)  // the kernel's own rounding of a particle of weight w_ref
+    a.qw_ref[s] = a.Z[s] * (int)std::rint((R)d.w_ref * a.sw);
   size_t slot = 0;
   pic_status ps = ev_begin(r, 0, st, &slot);
   if (ps) return ps;
@@ -282,8 +289,8 @@ pic_status launch_field(pic_run* r, hipStream_t st) {
   const Derived& d = r->d;
   const int p = (int)(r->step & 1);
   FieldArgs<R> f{};
-  f.in = fdev<R>(r->F[p]);
-  f.out = fdev<R>(r->F[p ^ 1]);
+  f.in = fdev<R>(r, p);
+  f.out = fdev<R>(r, p ^ 1);
   for (int k = 0; k < 3; ++k) {
     f.J[k] = (const long long*)r->J[p][k];
     f.Jnext[k] = r->J[p ^ 1][k];
@@ -385,7 +392,7 @@ pic_status do_diag(pic_run* r, pic_diag_out* out, hipStream_t st) {
   DiagArgs<R> p{};
   for (int s = 0; s < 2; ++s) p.sp[s] = dev<R>(r->sp[s][r->pp]);
   p.count = r->count + 2 * r->pp;
-  p.f = fdev<R>(r->F[r->step & 1]);
+  p.f = fdev<R>(r, (int)(r->step & 1));
   p.Ex_int = r->Ex_int;
   p.rho = r->rho;
   p.part = r->part;
@@ -578,12 +585,22 @@ pic_status pic_get_state(pic_run* r, pic_state* st, void* stream) {
         (ps = pull(o.ry, b.ry, 4)) || (ps = pull(o.rz, b.rz, 4)))
       return ps;
   }
-  void* const* F = r->F[r->step & 1];
-  void* outs[5] = {st->Ex, st->Ey, st->Ez, st->By, st->Bz};
-  const size_t len[5] = {(size_t)d.nx + 2, (size_t)d.nx + 1, (size_t)d.nx + 1, (size_t)d.nx + 2,
-                         (size_t)d.nx + 2};
-  for (int k = 0; k < 5; ++k)
-    if (outs[k]) HIP_TRY(hipMemcpy(outs[k], F[k], len[k] * rs, hipMemcpyDeviceToHost));
+  {  // de-interleave the fields of the current step
+    const int p = (int)(r->step & 1);
+    std::vector<char> nb((size_t)(d.nx + 1) * 2 * rs), hb((size_t)(d.nx + 2) * 4 * rs);
+    HIP_TRY(hipMemcpy(nb.data(), r->FN[p], nb.size(), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(hb.data(), r->FH[p], hb.size(), hipMemcpyDeviceToHost));
+    void* outs[5] = {st->Ex, st->Ey, st->Ez, st->By, st->Bz};
+    for (int k = 0; k < 5; ++k) {
+      if (!outs[k]) continue;
+      const bool node = (k == 1 || k == 2);
+      const size_t len = node ? d.nx + 1 : d.nx + 2, stride = node ? 2 : 4;
+      const size_t comp = k == 0 ? 0 : k == 1 ? 0 : k == 2 ? 1 : k == 3 ? 1 : 2;
+      const char* src = node ? nb.data() : hb.data();
+      for (size_t i = 0; i < len; ++i)
+        std::memcpy(static_cast<char*>(outs[k]) + i * rs, src + (i * stride + comp) * rs, rs);
+    }
+  }
   if (st->Ex_int)
     HIP_TRY(hipMemcpy(st->Ex_int, r->Ex_int, (d.nx + 2) * sizeof(long long), hipMemcpyDeviceToHost));
   int64_t* js[3] = {st->Jx_int, st->Jy_int, st->Jz_int};
@@ -605,8 +622,8 @@ pic_status pic_set_state(pic_run* r, const pic_state* st, void* stream) {
     // move the fields to the buffer parity of the new step
     const int po = (int)(r->step & 1), pn = (int)(st->step & 1);
     if (po != pn) {
-      for (int k = 0; k < 5; ++k)
-        HIP_TRY(hipMemcpy(r->F[pn][k], r->F[po][k], (size_t)(d.nx + 2) * rs, hipMemcpyDeviceToDevice));
+      HIP_TRY(hipMemcpy(r->FN[pn], r->FN[po], (size_t)(d.nx + 1) * 2 * rs, hipMemcpyDeviceToDevice));
+      HIP_TRY(hipMemcpy(r->FH[pn], r->FH[po], (size_t)(d.nx + 2) * 4 * rs, hipMemcpyDeviceToDevice));
     }
     r->step = st->step;
     HIP_TRY(hipMemcpy(r->step_dev, &r->step, sizeof(long long), hipMemcpyHostToDevice));
@@ -651,12 +668,26 @@ pic_status pic_set_state(pic_run* r, const pic_state* st, void* stream) {
     for (int p = 0; p < 2; ++p)
       for (int k = 0; k < 3; ++k) HIP_TRY(hipMemset(r->J[p][k], 0, (d.nx + 3) * sizeof(long long)));
   }
-  void* const* F = r->F[r->step & 1];
-  const void* ins[5] = {st->Ex, st->Ey, st->Ez, st->By, st->Bz};
-  const size_t len[5] = {(size_t)d.nx + 2, (size_t)d.nx + 1, (size_t)d.nx + 1, (size_t)d.nx + 2,
-                         (size_t)d.nx + 2};
-  for (int k = 0; k < 5; ++k)
-    if (ins[k]) HIP_TRY(hipMemcpy(F[k], ins[k], len[k] * rs, hipMemcpyHostToDevice));
+  {  // interleave the given fields into the current step's buffers
+    const int p = (int)(r->step & 1);
+    const void* ins[5] = {st->Ex, st->Ey, st->Ez, st->By, st->Bz};
+    if (ins[0] || ins[1] || ins[2] || ins[3] || ins[4]) {
+      std::vector<char> nb((size_t)(d.nx + 1) * 2 * rs), hb((size_t)(d.nx + 2) * 4 * rs);
+      HIP_TRY(hipMemcpy(nb.data(), r->FN[p], nb.size(), hipMemcpyDeviceToHost));
+      HIP_TRY(hipMemcpy(hb.data(), r->FH[p], hb.size(), hipMemcpyDeviceToHost));
+      for (int k = 0; k < 5; ++k) {
+        if (!ins[k]) continue;
+        const bool node = (k == 1 || k == 2);
+        const size_t len = node ? d.nx + 1 : d.nx + 2, stride = node ? 2 : 4;
+        const size_t comp = k == 0 ? 0 : k == 1 ? 0 : k == 2 ? 1 : k == 3 ? 1 : 2;
+        char* dst = node ? nb.data() : hb.data();
+        for (size_t i = 0; i < len; ++i)
+          std::memcpy(dst + (i * stride + comp) * rs, static_cast<const char*>(ins[k]) + i * rs, rs);
+      }
+      HIP_TRY(hipMemcpy(r->FN[p], nb.data(), nb.size(), hipMemcpyHostToDevice));
+      HIP_TRY(hipMemcpy(r->FH[p], hb.data(), hb.size(), hipMemcpyHostToDevice));
+    }
+  }
   if (st->Ex_int)
     HIP_TRY(hipMemcpy(r->Ex_int, st->Ex_int, (d.nx + 2) * sizeof(long long), hipMemcpyHostToDevice));
   const int64_t* js[3] = {st->Jx_int, st->Jy_int, st->Jz_int};

@@ -85,12 +85,13 @@ def test_quiet_start_matches_oracle():
 
 
 # --------------------------------------------------------------------------- move + deposit
-@pytest.mark.parametrize("n_e,n_i,box,ordered", [
-    (3000, 700, 4.0, True),      # wide tiles: few private LDS copies per node
-    (40000, 9000, 4.0, True),    # dense tiles: one LDS copy per lane
-    (2500, 900, 20.0, False),    # tiles spanning > 1020 cells: global atomics
+@pytest.mark.parametrize("n_e,n_i,box,ordered,mixed_w", [
+    (3000, 700, 4.0, True, False),      # wide tiles: few private LDS copies per node
+    (40000, 9000, 4.0, True, False),    # dense tiles: one LDS copy per lane
+    (2500, 900, 20.0, False, False),    # tiles spanning > 1020 cells: global atomics
+    (40000, 9000, 4.0, True, True),     # weights other than the reference weight
 ])
-def test_move_and_deposit_bit_exact_without_fields(n_e, n_i, box, ordered):
+def test_move_and_deposit_bit_exact_without_fields(n_e, n_i, box, ordered, mixed_w):
     # E = B = 0: the push leaves u unchanged bit for bit, so cell, offset and
     # the integer currents must equal the contract evaluated on the inputs
     cfg = preset("c1", box_lambda=box, x_foil=1.0)
@@ -99,6 +100,10 @@ def test_move_and_deposit_bit_exact_without_fields(n_e, n_i, box, ordered):
     run = _run(cfg, capacity=max(n_e, n_i))
     pe = random_particles(10 + n_e, n_e, 2, n - 2, sim.w_ref, u_lo=1e-3, u_hi=1e3, sort=ordered)
     pi = random_particles(11 + n_e, n_i, 2, n - 2, sim.w_ref, u_lo=1e-3, u_hi=1e2, sort=ordered)
+    if mixed_w:  # every third particle carries 0.37, 1.6 or 2.9 times the reference weight
+        for p in (pe, pi):
+            f = np.array([1.0, 0.37, 1.0, 1.6, 1.0, 2.9])[np.arange(len(p["w"])) % 6]
+            p["w"] = (p["w"] * f).astype(np.float32).astype(np.float64)
     run.set_state({0: pe, 1: pi}, fields=_zero_fields(n), step=0)
     run.push_deposit()
     st = run.get_state()
