@@ -4,10 +4,14 @@ protons per unit energy).
 TEST INFRASTRUCTURE ONLY (see package header).
 
 Reading: kinetic energy per proton E = (gamma - 1) M m_e c^2 with
-m_e c^2 = 0.51099895 MeV; weighted histogram on [0, e_max]; the peak is the
-mode refined by a parabola through the three bins around it; the width is
-the full width at half maximum, found by linear interpolation on both
-flanks.  Pins: exact peak and width of sampled Gaussians (tests).
+m_e c^2 = 0.51099895 MeV; weighted histogram f(E) on [0, e_max].  The
+spectra of Section 4 carry a low-energy tail next to the quasi-monoenergetic
+bunch, and the plain mode can jump between them; the "peak" is therefore the
+bunch that carries the most energy: the maximum of E f(E), refined by a
+parabola through the three bins around it.  The width is the full width at
+half maximum of f(E) around that bin, found by linear interpolation on both
+flanks.  Pins: sampled Gaussians, whose E f(E) peaks at
+(mu + sqrt(mu^2 + 4 sigma^2)) / 2 and whose FWHM is 2 sqrt(2 ln 2) sigma.
 """
 from __future__ import annotations
 
@@ -31,10 +35,11 @@ def peak_and_fwhm(h, edges):
     h = np.asarray(h, dtype=np.float64)
     centers = 0.5 * (edges[:-1] + edges[1:])
     de = edges[1] - edges[0]
-    k = int(np.argmax(h))
+    he = h * centers
+    k = int(np.argmax(he))
     peak = centers[k]
     if 0 < k < h.size - 1:
-        y0, y1, y2 = h[k - 1], h[k], h[k + 1]
+        y0, y1, y2 = he[k - 1], he[k], he[k + 1]
         den = y0 - 2.0 * y1 + y2
         if den != 0.0:
             peak += 0.5 * de * (y0 - y2) / den

@@ -28,11 +28,13 @@ def test_uniform24_is_uniform():
 
 def test_peak_and_fwhm_of_a_gaussian():
     r = np.random.default_rng(0)
-    mu, sig = 120.0, 7.0
+    mu, sig = 40.0, 7.0
     E = r.normal(mu, sig, size=2_000_000)
     h, edges = spectrum.histogram(E, np.ones_like(E), 400, 250.0)
     peak, width = spectrum.peak_and_fwhm(h, edges)
-    assert peak == pytest.approx(mu, abs=0.3)
+    # maximum of E exp(-(E - mu)^2 / (2 sigma^2))
+    assert peak == pytest.approx(0.5 * (mu + np.sqrt(mu * mu + 4 * sig * sig)), abs=0.3)
+    assert abs(peak - mu) > 0.3  # the energy weighting is resolved
     assert width == pytest.approx(2 * np.sqrt(2 * np.log(2)) * sig, rel=0.02)
 
 
