@@ -85,6 +85,35 @@ def cpu_baseline(cfg, budget_s=20.0, max_steps=8):
                        f"({n} particles; numpy, single thread)")
 
 
+def serve_bench(n_runs=256, rate=20.0, seed=0, max_slots=64, budget_gb=64.0):
+    """Serving form: a Poisson stream of independent laser-foil requests
+    (a0, polarisation, density, thickness, size and length randomised),
+    continuously batched; latency = completion - arrival."""
+    import numpy as np
+
+    from paper_1008_1685_amd.serve import Server, run_steps
+    from workloads import poisson_stream
+
+    reqs = poisson_stream(seed, n_runs=n_runs, rate=rate)
+    max_p = max(2 * r["cfg"]["ppc"] * round(r["cfg"]["thickness"] * r["cfg"]["cells_per_lambda"])
+                for r in reqs)
+    max_c = max(round(r["cfg"]["box_lambda"] * r["cfg"]["cells_per_lambda"]) for r in reqs)
+    srv = Server(budget_bytes=int(budget_gb * 2 ** 30), max_slots=max_slots,
+                 max_particles=max_slots * max_p, max_cells=max_slots * (max_c + 8))
+    t0 = time.perf_counter()
+    recs = srv.serve(reqs)
+    wall = time.perf_counter() - t0
+    lat = np.array([r["latency"] for r in recs])
+    pushes = sum(r["particles"] * r["steps"] for r in recs)
+    bad = sum(1 for r in recs if r["diag"]["gauss_int"] != 0 or r["diag"]["nonfinite"])
+    return dict(workload=f"{n_runs} Poisson requests at {rate:g}/s (seed {seed}); a0 U[50,500], "
+                         "LP/CP, n0 U[50,150], thickness U[0.5,2], 1e4-1e6 particles, 30-80 periods",
+                requests=len(recs), p50_s=float(np.percentile(lat, 50)),
+                p99_s=float(np.percentile(lat, 99)), mean_s=float(lat.mean()), wall_s=wall,
+                pushes=float(pushes), pushes_per_s=pushes / wall,
+                peak_resident_bytes=srv.peak_bytes, max_slots=max_slots, failed_checks=bad)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +123,7 @@ def main():
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--no-side-runs", action="store_true",
                     help="skip the RR-off and FP64 comparison runs and the CPU baseline")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving-form measurement")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
     args = ap.parse_args()
     if args.gpus != 1:
@@ -156,6 +186,8 @@ def main():
                                paper="about +10% compute time with RR (Section 3)")
         line["fp64_path"] = dict(pushes_per_s=v_64, speedup_fp32_over_fp64=value / v_64)
         line["cpu_baseline"] = cpu_baseline(cfg)
+    if not args.no_serve:
+        line["serving"] = serve_bench()
     print(json.dumps(line), flush=True)
 
 

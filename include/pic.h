@@ -225,6 +225,57 @@ pic_status pic_timing_enable(struct pic_run* run, int32_t enable);
 pic_status pic_timing_read(struct pic_run* run, double ms[3], int64_t launches[3],
                            void* stream);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of independent runs (laser-foil requests of
+ * uneven size).  A batch keeps a device table of up to max_slots resident
+ * runs and advances all of them with the same launches: per quantum
+ * (= the runs' sort_interval steps) one sort stage (hist, scan, scatter) and
+ * then, per step, one push-deposit, one field and one tick launch whose
+ * work-groups are spread over the runs' tiles.  Each run derives its buffer
+ * parities, sort schedule and laser clock from its own device step counter,
+ * so the quantum is captured once into a HIP graph and replayed while runs
+ * join and leave; every run executes exactly the kernels it would execute
+ * alone, so its fields and integer currents are bit-identical to a run
+ * stepped alone (particle order within a cell may differ).
+ * The caller owns the batch workspace (pic_batch_workspace_bytes) and every
+ * run's workspace; admission by device-memory budget is the caller's policy
+ * (the Python server implements one).  The stream must not be the null
+ * stream (graph capture).  A run inside a batch rejects the single-run
+ * entry points (PIC_EBUSY) until it is released.
+ * ------------------------------------------------------------------------ */
+typedef struct pic_batch pic_batch;
+
+/* Bytes of the batch workspace (host-only). */
+pic_status pic_batch_workspace_bytes(int32_t precision, int32_t max_slots, size_t* bytes);
+
+/* Create a batch.  max_particles / max_cells bound the total particles
+ * (both species) and cells of all resident runs; they size the captured
+ * launches.  Blocking (initialises the slot table on `stream`). */
+pic_status pic_batch_create(int32_t precision, int32_t max_slots, int32_t quantum,
+                            int64_t max_particles, int64_t max_cells, void* d_ws,
+                            size_t ws_bytes, void* stream, pic_batch** out);
+
+/* Admit a run at step 0 (fresh from pic_init) to be advanced to step
+ * n_steps.  Its sort_interval must equal the quantum and its precision the
+ * batch's.  PIC_EBUSY if no slot or work capacity is free.  Blocking. */
+pic_status pic_batch_admit(pic_batch* b, struct pic_run* run, int64_t n_steps, void* stream,
+                           int32_t* slot);
+
+/* Enqueue n_quanta graph replays (quantum steps each) for every resident
+ * run; runs stop at their n_steps.  Async.  The first call captures the graph. */
+pic_status pic_batch_step(pic_batch* b, int32_t n_quanta, void* stream);
+
+/* Copy every slot's current step to steps[max_slots] (-1 for free slots).
+ * Blocking. */
+pic_status pic_batch_poll(pic_batch* b, int64_t* steps, void* stream);
+
+/* Detach the run of `slot` (its state stays in its workspace; pic_diag and
+ * the other single-run calls work again).  Blocking. */
+pic_status pic_batch_release(pic_batch* b, int32_t slot, void* stream);
+
+/* Destroy the batch (detaches resident runs; the workspace stays the caller's). */
+void pic_batch_free(pic_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -137,6 +137,15 @@ SIGNATURES = {
     "pic_timing_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "pic_timing_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                   C.c_void_p]),
+    "pic_batch_workspace_bytes": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
+    "pic_batch_create": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int64, C.c_int64,
+                                   C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "pic_batch_admit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                  C.POINTER(C.c_int32)]),
+    "pic_batch_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "pic_batch_poll": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.c_void_p]),
+    "pic_batch_release": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "pic_batch_free": (None, [C.c_void_p]),
 }
 
 _lib = None

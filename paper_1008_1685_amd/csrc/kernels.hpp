@@ -36,6 +36,9 @@ namespace pic {
 #ifndef PIC_PUSH_PREFETCH
 #define PIC_PUSH_PREFETCH 1
 #endif
+#ifndef PIC_PUSH_MIN_WAVES
+#define PIC_PUSH_MIN_WAVES 0
+#endif
 
 constexpr int kDead = INT_MIN;        // cell index of a removed particle
 constexpr int kThreads = 256;         // push work-group
@@ -98,6 +101,7 @@ struct PushArgs {
   int comp;                      // compensated RR accumulation (fp32 only)
   R sw;                          // 256 / w_ref (charge-weight scale)
   int qw_ref[2];                 // charge weight of a particle of weight w_ref
+  int ntiles;                    // tiles of both species
 };
 
 // ---------------------------------------------------------------- helpers
@@ -517,9 +521,8 @@ __device__ __forceinline__ void push_tile(const PushArgs<R>& a, int s, int tile,
 }
 
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_push(PushArgs<R> a) {
-  __shared__ unsigned long long lds[kLdsSlots];
-  const int tile = blockIdx.x;
+__device__ __forceinline__ void push_one_tile(const PushArgs<R>& a, int tile,
+                                              unsigned long long* lds) {
   const int s = tile < a.tiles0 ? 0 : 1;
   const int tl = s ? tile - a.tiles0 : tile;
   const int n = (int)a.count[s];
@@ -535,6 +538,19 @@ __global__ __launch_bounds__(kThreads) void k_push(PushArgs<R> a) {
   }
 }
 
+#if PIC_PUSH_MIN_WAVES > 0
+#define PIC_PUSH_BOUNDS __launch_bounds__(kThreads, PIC_PUSH_MIN_WAVES)
+#else
+#define PIC_PUSH_BOUNDS __launch_bounds__(kThreads)
+#endif
+
+// one work-group per tile
+template <typename R>
+__global__ PIC_PUSH_BOUNDS void k_push(PushArgs<R> a) {
+  __shared__ unsigned long long lds[kLdsSlots];
+  push_one_tile(a, (int)blockIdx.x, lds);
+}
+
 // ---------------------------------------------------------------- fields
 template <typename R>
 struct FieldArgs {
@@ -544,6 +560,7 @@ struct FieldArgs {
   long long* Ex_int;
   double* budget;                 // [0] E_in, [1] E_out_left, [2] E_out_right
   long long* step;                // device step counter
+  int tick;                       // 1: work-group 0 advances *step after the update
   int nx;
   R a;                            // dt / dx
   R dt;
@@ -571,14 +588,14 @@ __device__ __forceinline__ double envelope(double t, double tr, double tf, doubl
 }
 
 template <typename R>
-__global__ __launch_bounds__(kFieldChunk) void k_field(FieldArgs<R> p) {
+__device__ __forceinline__ void field_chunk(const FieldArgs<R>& p, int chunk) {
   constexpr int CH = kFieldChunk;
   __shared__ R sEy[CH + 3], sEz[CH + 3];      // E^n, nodes i0-2 .. i0+CH
   __shared__ R sBy[CH + 2], sBz[CH + 2];      // B, half-nodes i0-1 .. i0+CH
   __shared__ R sJy[CH + 1], sJz[CH + 1];      // J, nodes i0-1 .. i0+CH-1
   __shared__ R nEy[CH + 1], nEz[CH + 1];      // E^{n+1}, nodes i0-1 .. i0+CH-1
   const int t = threadIdx.x;
-  const int i0 = blockIdx.x * CH;
+  const int i0 = chunk * CH;
   const int n = p.nx;
   const R a = p.a, ha = R(0.5) * p.a, dt = p.dt;
 
@@ -658,7 +675,7 @@ __global__ __launch_bounds__(kFieldChunk) void k_field(FieldArgs<R> p) {
     const double L1 = eyl - bzl, L2 = ezl + byl;
     p.budget[0] += p.dtd * (ey_in * ey_in + ez_in * ez_in);
     p.budget[1] += p.dtd * 0.25 * (L1 * L1 + L2 * L2);
-    *p.step += 1;
+    if (p.tick) *p.step += 1;
   }
   if (t == 0 && i0 <= n && n < i0 + CH) {
     const int kn = n - (i0 - 2), ke = n - (i0 - 1), kb = n - (i0 - 1);
@@ -694,6 +711,11 @@ __global__ __launch_bounds__(kFieldChunk) void k_field(FieldArgs<R> p) {
     p.Jnext[1][i0 + t] = 0ull;
     p.Jnext[2][i0 + t] = 0ull;
   }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kFieldChunk) void k_field(FieldArgs<R> p) {
+  field_chunk<R>(p, (int)blockIdx.x);
 }
 
 // ---------------------------------------------------------------- sort
@@ -757,11 +779,11 @@ __device__ __forceinline__ void tile_range(const int* cl, int& lo, int& hi, int*
 // per-cell particle counts: LDS histogram over the tile's cell window,
 // then one global atomic per occupied cell and tile
 template <typename R>
-__global__ __launch_bounds__(kSortThreads) void k_sort_hist(SortArgs<R> p) {
+__device__ __forceinline__ void sort_hist_block(const SortArgs<R>& p, int blk) {
   __shared__ int cnt[kSortWin];
   __shared__ int sm[8];
-  const int s = blockIdx.x < p.blocks0 ? 0 : 1;
-  const int b = s ? blockIdx.x - p.blocks0 : blockIdx.x;
+  const int s = blk < p.blocks0 ? 0 : 1;
+  const int b = s ? blk - p.blocks0 : blk;
   const long long n = p.count[s];
   const long long base = (long long)b * kSortTile;
   if (base >= n) return;
@@ -789,13 +811,16 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(SortArgs<R> p) {
   }
 }
 
-// exclusive scan of the per-cell counts; one work-group per species; the
-// alive count goes to new_count (the count slot of the destination arrays)
-__global__ __launch_bounds__(1024) void k_sort_scan(int* cnt0, int* cnt1, int* cur0, int* cur1,
-                                                    long long* new_count, int nx) {
+template <typename R>
+__global__ __launch_bounds__(kSortThreads) void k_sort_hist(SortArgs<R> p) {
+  sort_hist_block<R>(p, (int)blockIdx.x);
+}
+
+// exclusive scan of the per-cell counts of one species (one work-group);
+// the alive count goes to *new_count (the count slot of the destination
+// arrays) and the counts are cleared for the next histogram
+__device__ __forceinline__ void sort_scan_species(int* cnt, int* cur, long long* new_count, int nx) {
   __shared__ int part[1024];
-  int* cnt = blockIdx.x ? cnt1 : cnt0;
-  int* cur = blockIdx.x ? cur1 : cur0;
   const int t = threadIdx.x;
   const int per = (nx + 1023) / 1024;
   const int lo = min(nx, t * per), hi = min(nx, lo + per);
@@ -816,18 +841,26 @@ __global__ __launch_bounds__(1024) void k_sort_scan(int* cnt0, int* cnt1, int* c
     run += c;
     cnt[j] = 0;
   }
-  if (t == 1023) new_count[blockIdx.x] = part[1023];
+  if (t == 1023) *new_count = part[1023];
+}
+
+__global__ __launch_bounds__(1024) void k_sort_scan(int* cnt0, int* cnt1, int* cur0, int* cur1,
+                                                    long long* new_count, int nx) {
+  if (blockIdx.x == 0)
+    sort_scan_species(cnt0, cur0, new_count, nx);
+  else
+    sort_scan_species(cnt1, cur1, new_count + 1, nx);
 }
 
 // scatter to the destination arrays: each tile claims, per occupied cell,
 // one contiguous range of the cell's bucket with a single global atomic and
 // hands out positions inside it through an LDS counter
 template <typename R>
-__global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortArgs<R> p) {
+__device__ __forceinline__ void sort_scatter_block(const SortArgs<R>& p, int blk) {
   __shared__ int cnt[kSortWin];
   __shared__ int sm[8];
-  const int s = blockIdx.x < p.blocks0 ? 0 : 1;
-  const int b = s ? blockIdx.x - p.blocks0 : blockIdx.x;
+  const int s = blk < p.blocks0 ? 0 : 1;
+  const int b = s ? blk - p.blocks0 : blk;
   const long long n = p.count[s];
   const long long base = (long long)b * kSortTile;
   if (base >= n) return;
@@ -876,6 +909,118 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortArgs<R> p) {
       dst.rz[j] = src.rz[i];
     }
   }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortArgs<R> p) {
+  sort_scatter_block<R>(p, (int)blockIdx.x);
+}
+
+// ---------------------------------------------------------------- batched runs
+// One slot per resident run.  Everything a step needs is derived from the
+// run's device step counter n: sort due iff n > 0 and n % K == 0, particle
+// buffer parity (n / K) & 1 for the push (the sort at step n reads parity
+// (n / K - 1) & 1), field and current parity n & 1, laser time from n.  A
+// captured sequence of batched launches can therefore be replayed while
+// runs join and leave: only the slot table and the work ranges change.
+template <typename R>
+struct SlotDev {
+  PushArgs<R> push[2][2];   // [particle parity][field parity]
+  FieldArgs<R> field[2];    // [field parity]; tick = 0 (k_tick_batch advances)
+  SortArgs<R> sort[2];      // [source particle parity]
+  int* cnt[2];
+  int* cur[2];
+  long long* count;         // [parity][species]
+  long long* step;          // the run's device step counter
+  long long target;         // the run stops once *step reaches target
+  int sort_interval;
+  int nx;
+};
+
+// slot whose work range [start[s], start[s + 1]) holds block b
+__device__ __forceinline__ int find_slot(const int* start, int n, int b) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int m = (lo + hi) >> 1;
+    if (start[m] <= b)
+      lo = m;
+    else
+      hi = m;
+  }
+  return lo;
+}
+
+template <typename R>
+__global__ PIC_PUSH_BOUNDS void k_push_batch(const SlotDev<R>* slots, const int* start, int n) {
+  __shared__ unsigned long long lds[kLdsSlots];
+  const int b = (int)blockIdx.x;
+  if (b >= start[n]) return;
+  const int sl = find_slot(start, n, b);
+  const SlotDev<R>& S = slots[sl];
+  const long long st = *S.step;
+  if (st >= S.target) return;
+  const int pp = (int)((st / S.sort_interval) & 1), fp = (int)(st & 1);
+  push_one_tile<R>(S.push[pp][fp], b - start[sl], lds);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kFieldChunk) void k_field_batch(const SlotDev<R>* slots,
+                                                            const int* start, int n) {
+  const int b = (int)blockIdx.x;
+  if (b >= start[n]) return;
+  const int sl = find_slot(start, n, b);
+  const SlotDev<R>& S = slots[sl];
+  const long long st = *S.step;
+  if (st >= S.target) return;
+  field_chunk<R>(S.field[st & 1], b - start[sl]);
+}
+
+template <typename R>
+__device__ __forceinline__ bool sort_due(const SlotDev<R>& S, int* q) {
+  const long long st = *S.step;
+  if (st >= S.target || st <= 0 || st % S.sort_interval) return false;
+  *q = (int)((st / S.sort_interval - 1) & 1);
+  return true;
+}
+
+template <typename R>
+__global__ __launch_bounds__(kSortThreads) void k_sort_hist_batch(const SlotDev<R>* slots,
+                                                                 const int* start, int n) {
+  const int b = (int)blockIdx.x;
+  if (b >= start[n]) return;
+  const int sl = find_slot(start, n, b);
+  int q;
+  if (!sort_due(slots[sl], &q)) return;
+  sort_hist_block<R>(slots[sl].sort[q], b - start[sl]);
+}
+
+template <typename R>
+__global__ __launch_bounds__(1024) void k_sort_scan_batch(const SlotDev<R>* slots, int n) {
+  const int sl = (int)blockIdx.x >> 1, sp = (int)blockIdx.x & 1;
+  if (sl >= n) return;
+  const SlotDev<R>& S = slots[sl];
+  int q;
+  if (!sort_due(S, &q)) return;
+  sort_scan_species(S.cnt[sp], S.cur[sp], S.count + 2 * (q ^ 1) + sp, S.nx);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kSortThreads) void k_sort_scatter_batch(const SlotDev<R>* slots,
+                                                                    const int* start, int n) {
+  const int b = (int)blockIdx.x;
+  if (b >= start[n]) return;
+  const int sl = find_slot(start, n, b);
+  int q;
+  if (!sort_due(slots[sl], &q)) return;
+  sort_scatter_block<R>(slots[sl].sort[q], b - start[sl]);
+}
+
+template <typename R>
+__global__ void k_tick_batch(const SlotDev<R>* slots, int n) {
+  const int sl = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (sl >= n) return;
+  long long* st = slots[sl].step;
+  if (*st < slots[sl].target) *st += 1;
 }
 
 // ---------------------------------------------------------------- init

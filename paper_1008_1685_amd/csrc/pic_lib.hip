@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstddef>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -141,6 +142,7 @@ struct pic_run {
   DiagOutDev* dout;
   unsigned long long* hist;
   int tiles_max;
+  struct pic_batch* batch = nullptr;  // set while the run is stepped by a batch
   // timing
   bool timing = false;
   std::vector<TimingRec> ev;
@@ -248,17 +250,24 @@ pic_status ev_end(pic_run* r, hipStream_t st, size_t slot) {
   return PIC_OK;
 }
 
+bool comp_on(const pic_run* r) {
+  return r->cfg.rr && r->cfg.rr_compensated && r->cfg.precision == PIC_FP32;
+}
+
+int sort_blocks_for(long long n) {
+  return (int)std::max<long long>(1, (n + kSortTile - 1) / kSortTile);
+}
+
+// Kernel arguments of run r for particle buffer parity pp and field parity fp.
 template <typename R>
-pic_status launch_push(pic_run* r, hipStream_t st) {
+PushArgs<R> make_push_args(const pic_run* r, int pp, int fp) {
   const Derived& d = r->d;
-  const int t0 = tiles_for(r->n_max[0]), t1 = tiles_for(r->n_max[1]);
-  if (t0 + t1 == 0) return PIC_OK;
   PushArgs<R> a{};
-  for (int s = 0; s < 2; ++s) a.sp[s] = dev<R>(r->sp[s][r->pp]);
-  a.count = r->count + 2 * r->pp;
-  a.tiles0 = t0;
-  a.f = fdev<R>(r, (int)(r->step & 1));
-  for (int k = 0; k < 3; ++k) a.J[k] = r->J[r->step & 1][k];
+  for (int s = 0; s < 2; ++s) a.sp[s] = dev<R>(r->sp[s][pp]);
+  a.count = r->count + 2 * pp;
+  a.tiles0 = tiles_for(r->n_max[0]);
+  a.f = fdev<R>(r, fp);
+  for (int k = 0; k < 3; ++k) a.J[k] = r->J[fp][k];
   a.acc = r->acc;
   a.flags = r->flags;
   a.nx = d.nx;
@@ -272,22 +281,17 @@ pic_status launch_push(pic_run* r, hipStream_t st) {
   a.mass[0] = 1.0;
   a.mass[1] = r->cfg.mass_ratio;
   a.rr0 = r->cfg.rr != 0;
-  a.comp = (r->cfg.rr && r->cfg.rr_compensated && r->cfg.precision == PIC_FP32) ? 1 : 0;
+  a.comp = comp_on(r) ? 1 : 0;
   a.sw = (R)(256.0 / d.w_ref);
   for (int s = 0; s < 2; ++s)  // the kernel's own rounding of a particle of weight w_ref
     a.qw_ref[s] = a.Z[s] * (int)std::rint((R)d.w_ref * a.sw);
-  size_t slot = 0;
-  pic_status ps = ev_begin(r, 0, st, &slot);
-  if (ps) return ps;
-  hipLaunchKernelGGL(k_push<R>, dim3(t0 + t1), dim3(kThreads), 0, st, a);
-  HIP_TRY(hipGetLastError());
-  return ev_end(r, st, slot);
+  a.ntiles = a.tiles0 + tiles_for(r->n_max[1]);
+  return a;
 }
 
 template <typename R>
-pic_status launch_field(pic_run* r, hipStream_t st) {
+FieldArgs<R> make_field_args(const pic_run* r, int p, int tick) {
   const Derived& d = r->d;
-  const int p = (int)(r->step & 1);
   FieldArgs<R> f{};
   f.in = fdev<R>(r, p);
   f.out = fdev<R>(r, p ^ 1);
@@ -298,6 +302,7 @@ pic_status launch_field(pic_run* r, hipStream_t st) {
   f.Ex_int = r->Ex_int;
   f.budget = r->budget;
   f.step = r->step_dev;
+  f.tick = tick;
   f.nx = d.nx;
   f.a = (R)r->cfg.cfl;
   f.dt = (R)d.dt;
@@ -312,11 +317,46 @@ pic_status launch_field(pic_run* r, hipStream_t st) {
   f.tr = 2.0 * M_PI * r->cfg.t_rise;
   f.tf = 2.0 * M_PI * r->cfg.t_flat;
   f.tl = 2.0 * M_PI * r->cfg.t_fall;
-  const int blocks = (d.nx + 3 + kFieldChunk - 1) / kFieldChunk;
+  return f;
+}
+
+int field_blocks_for(const pic_run* r) { return (r->d.nx + 3 + kFieldChunk - 1) / kFieldChunk; }
+
+template <typename R>
+SortArgs<R> make_sort_args(const pic_run* r, int pp) {
+  SortArgs<R> p{};
+  for (int s = 0; s < 2; ++s) {
+    p.src[s] = dev<R>(r->sp[s][pp]);
+    p.dst[s] = dev<R>(r->sp[s][pp ^ 1]);
+    p.cnt[s] = r->cnt[s];
+    p.cursor[s] = r->cursor[s];
+  }
+  p.count = r->count + 2 * pp;
+  p.nx = r->d.nx;
+  p.comp = comp_on(r) ? 1 : 0;
+  p.blocks0 = sort_blocks_for(r->n_max[0]);
+  return p;
+}
+
+template <typename R>
+pic_status launch_push(pic_run* r, hipStream_t st) {
+  const PushArgs<R> a = make_push_args<R>(r, r->pp, (int)(r->step & 1));
+  if (a.ntiles == 0) return PIC_OK;
+  size_t slot = 0;
+  pic_status ps = ev_begin(r, 0, st, &slot);
+  if (ps) return ps;
+  hipLaunchKernelGGL(k_push<R>, dim3(a.ntiles), dim3(kThreads), 0, st, a);
+  HIP_TRY(hipGetLastError());
+  return ev_end(r, st, slot);
+}
+
+template <typename R>
+pic_status launch_field(pic_run* r, hipStream_t st) {
+  const FieldArgs<R> f = make_field_args<R>(r, (int)(r->step & 1), 1);
   size_t slot = 0;
   pic_status ps = ev_begin(r, 1, st, &slot);
   if (ps) return ps;
-  hipLaunchKernelGGL(k_field<R>, dim3(blocks), dim3(kFieldChunk), 0, st, f);
+  hipLaunchKernelGGL(k_field<R>, dim3(field_blocks_for(r)), dim3(kFieldChunk), 0, st, f);
   HIP_TRY(hipGetLastError());
   ps = ev_end(r, st, slot);
   if (ps) return ps;
@@ -326,28 +366,14 @@ pic_status launch_field(pic_run* r, hipStream_t st) {
 
 template <typename R>
 pic_status launch_sort(pic_run* r, hipStream_t st) {
-  const Derived& d = r->d;
-  SortArgs<R> p{};
-  for (int s = 0; s < 2; ++s) {
-    p.src[s] = dev<R>(r->sp[s][r->pp]);
-    p.dst[s] = dev<R>(r->sp[s][r->pp ^ 1]);
-    p.cnt[s] = r->cnt[s];
-    p.cursor[s] = r->cursor[s];
-  }
-  p.count = r->count + 2 * r->pp;
-  p.nx = d.nx;
-  p.comp = (r->cfg.rr && r->cfg.rr_compensated && r->cfg.precision == PIC_FP32) ? 1 : 0;
-  auto blocks = [](long long n) {
-    return (int)std::max<long long>(1, (n + kSortTile - 1) / kSortTile);
-  };
-  p.blocks0 = blocks(r->n_max[0]);
-  const int grid = p.blocks0 + blocks(r->n_max[1]);
+  const SortArgs<R> p = make_sort_args<R>(r, r->pp);
+  const int grid = p.blocks0 + sort_blocks_for(r->n_max[1]);
   size_t slot = 0;
   pic_status ps = ev_begin(r, 2, st, &slot);
   if (ps) return ps;
   hipLaunchKernelGGL(k_sort_hist<R>, dim3(grid), dim3(kSortThreads), 0, st, p);
   hipLaunchKernelGGL(k_sort_scan, dim3(2), dim3(1024), 0, st, r->cnt[0], r->cnt[1], r->cursor[0],
-                     r->cursor[1], r->count + 2 * (r->pp ^ 1), d.nx);
+                     r->cursor[1], r->count + 2 * (r->pp ^ 1), r->d.nx);
   hipLaunchKernelGGL(k_sort_scatter<R>, dim3(grid), dim3(kSortThreads), 0, st, p);
   HIP_TRY(hipGetLastError());
   ps = ev_end(r, st, slot);
@@ -446,6 +472,121 @@ pic_status do_diag(pic_run* r, pic_diag_out* out, hipStream_t st) {
 
 size_t rsz(const pic_run* r) { return r->d.rsize; }
 
+
+// ---------------------------------------------------------------- batches
+size_t slot_bytes_for(int prec) {
+  return prec == PIC_FP32 ? sizeof(SlotDev<float>) : sizeof(SlotDev<double>);
+}
+
+}  // namespace
+
+struct pic_batch {
+  int prec;
+  int max_slots, quantum;
+  int cap[3];                 // work-group capacity: push, field, sort
+  char* tab;                  // device slot table
+  size_t slot_bytes;
+  int* start[3];              // device work ranges [max_slots + 1]
+  long long* dummy_step;      // step counter of free slots
+  long long* steps;           // [max_slots] gathered step counters
+  std::vector<pic_run*> runs;
+  std::vector<long long> target;
+  std::vector<int> nblk[3];
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+size_t batch_layout(int prec, int max_slots, pic_batch* b, char* base) {
+  Carver cv{base};
+  char* tab = cv.take<char>(slot_bytes_for(prec) * max_slots);
+  int* st[3];
+  for (int k = 0; k < 3; ++k) st[k] = cv.take<int>(max_slots + 1);
+  long long* dummy = cv.take<long long>(1);
+  long long* steps = cv.take<long long>(max_slots);
+  if (b) {
+    b->tab = tab;
+    for (int k = 0; k < 3; ++k) b->start[k] = st[k];
+    b->dummy_step = dummy;
+    b->steps = steps;
+  }
+  return cv.off + 256;
+}
+
+template <typename R>
+SlotDev<R> make_slot(const pic_batch* b, const pic_run* r, long long target) {
+  SlotDev<R> e{};
+  if (!r) {
+    e.step = b->dummy_step;
+    e.target = 0;
+    e.sort_interval = b->quantum;
+    return e;
+  }
+  for (int pp = 0; pp < 2; ++pp)
+    for (int fp = 0; fp < 2; ++fp) e.push[pp][fp] = make_push_args<R>(r, pp, fp);
+  for (int fp = 0; fp < 2; ++fp) e.field[fp] = make_field_args<R>(r, fp, 0);
+  for (int q = 0; q < 2; ++q) e.sort[q] = make_sort_args<R>(r, q);
+  for (int s = 0; s < 2; ++s) {
+    e.cnt[s] = r->cnt[s];
+    e.cur[s] = r->cursor[s];
+  }
+  e.count = r->count;
+  e.step = r->step_dev;
+  e.target = target;
+  e.sort_interval = r->cfg.sort_interval;
+  e.nx = r->d.nx;
+  return e;
+}
+
+template <typename R>
+pic_status write_slot(pic_batch* b, int slot, hipStream_t st) {
+  const SlotDev<R> e = make_slot<R>(b, b->runs[slot], b->target[slot]);
+  HIP_TRY(hipMemcpyAsync(b->tab + slot * b->slot_bytes, &e, sizeof(e), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return PIC_OK;
+}
+
+pic_status write_ranges(pic_batch* b, hipStream_t st) {
+  std::vector<int> h((size_t)3 * (b->max_slots + 1));
+  for (int k = 0; k < 3; ++k) {
+    int* o = h.data() + k * (b->max_slots + 1);
+    o[0] = 0;
+    for (int s = 0; s < b->max_slots; ++s) o[s + 1] = o[s] + b->nblk[k][s];
+    HIP_TRY(hipMemcpyAsync(b->start[k], o, (b->max_slots + 1) * sizeof(int), hipMemcpyHostToDevice, st));
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  return PIC_OK;
+}
+
+template <typename R>
+pic_status capture_batch(pic_batch* b, hipStream_t st) {
+  const SlotDev<R>* tab = reinterpret_cast<const SlotDev<R>*>(b->tab);
+  const int n = b->max_slots;
+  HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+  // every admitted run is at a multiple of the quantum here, so the sort
+  // (when due) is the first stage of the quantum
+  hipLaunchKernelGGL(k_sort_hist_batch<R>, dim3(b->cap[2]), dim3(kSortThreads), 0, st, tab, b->start[2], n);
+  hipLaunchKernelGGL(k_sort_scan_batch<R>, dim3(2 * n), dim3(1024), 0, st, tab, n);
+  hipLaunchKernelGGL(k_sort_scatter_batch<R>, dim3(b->cap[2]), dim3(kSortThreads), 0, st, tab, b->start[2], n);
+  for (int q = 0; q < b->quantum; ++q) {
+    hipLaunchKernelGGL(k_push_batch<R>, dim3(b->cap[0]), dim3(kThreads), 0, st, tab, b->start[0], n);
+    hipLaunchKernelGGL(k_field_batch<R>, dim3(b->cap[1]), dim3(kFieldChunk), 0, st, tab, b->start[1], n);
+    hipLaunchKernelGGL(k_tick_batch<R>, dim3((n + 255) / 256), dim3(256), 0, st, tab, n);
+  }
+  hipError_t e = hipStreamEndCapture(st, &b->graph);
+  if (e != hipSuccess) return fail(PIC_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  return PIC_OK;
+}
+
+__global__ void k_gather_steps(const char* tab, size_t slot_bytes, size_t step_off, int n,
+                               long long* out) {
+  const int s = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (s < n) out[s] = **reinterpret_cast<long long* const*>(tab + s * slot_bytes + step_off);
+}
+
+
 }  // namespace
 
 extern "C" {
@@ -501,26 +642,31 @@ pic_status pic_init(const pic_config* cfg, void* d_ws, size_t ws_bytes, void* st
 
 pic_status pic_step(pic_run* r, int64_t n, void* stream) {
   if (!r || n < 0) return fail(PIC_EINVAL, "null run or negative step count");
+  if (r->batch) return fail(PIC_EBUSY, "run is stepped by a batch; release it first");
   return r->d.prec == PIC_FP32 ? do_steps<float>(r, n, S(stream)) : do_steps<double>(r, n, S(stream));
 }
 
 pic_status pic_push_deposit(pic_run* r, void* stream) {
   if (!r) return fail(PIC_EINVAL, "null run");
+  if (r->batch) return fail(PIC_EBUSY, "run is stepped by a batch; release it first");
   return r->d.prec == PIC_FP32 ? launch_push<float>(r, S(stream)) : launch_push<double>(r, S(stream));
 }
 
 pic_status pic_field_advance(pic_run* r, void* stream) {
   if (!r) return fail(PIC_EINVAL, "null run");
+  if (r->batch) return fail(PIC_EBUSY, "run is stepped by a batch; release it first");
   return r->d.prec == PIC_FP32 ? launch_field<float>(r, S(stream)) : launch_field<double>(r, S(stream));
 }
 
 pic_status pic_sort(pic_run* r, void* stream) {
   if (!r) return fail(PIC_EINVAL, "null run");
+  if (r->batch) return fail(PIC_EBUSY, "run is stepped by a batch; release it first");
   return r->d.prec == PIC_FP32 ? launch_sort<float>(r, S(stream)) : launch_sort<double>(r, S(stream));
 }
 
 pic_status pic_diag(pic_run* r, pic_diag_out* out, void* stream) {
   if (!r || !out) return fail(PIC_EINVAL, "null run or output");
+  if (r->batch) return fail(PIC_EBUSY, "run is stepped by a batch; release it first");
   return r->d.prec == PIC_FP32 ? do_diag<float>(r, out, S(stream)) : do_diag<double>(r, out, S(stream));
 }
 
@@ -542,7 +688,7 @@ pic_status pic_get_info(const pic_run* r, pic_info* o) {
 }
 
 void pic_free(pic_run* r) {
-  if (!r) return;
+  if (!r || r->batch) return;
   for (auto& e : r->ev) {
     (void)hipEventDestroy(e.a);
     (void)hipEventDestroy(e.b);
@@ -552,6 +698,7 @@ void pic_free(pic_run* r) {
 
 pic_status pic_get_state(pic_run* r, pic_state* st, void* stream) {
   if (!r || !st) return fail(PIC_EINVAL, "null run or state");
+  if (r->batch) return fail(PIC_EBUSY, "run is stepped by a batch; release it first");
   hipStream_t s = S(stream);
   const Derived& d = r->d;
   const size_t rs = rsz(r);
@@ -614,6 +761,7 @@ pic_status pic_get_state(pic_run* r, pic_state* st, void* stream) {
 
 pic_status pic_set_state(pic_run* r, const pic_state* st, void* stream) {
   if (!r || !st) return fail(PIC_EINVAL, "null run or state");
+  if (r->batch) return fail(PIC_EBUSY, "run is stepped by a batch; release it first");
   hipStream_t s = S(stream);
   const Derived& d = r->d;
   const size_t rs = rsz(r);
@@ -745,6 +893,145 @@ pic_status pic_timing_read(pic_run* r, double ms[3], int64_t launches[3], void* 
     r->launches[k] = 0;
   }
   return PIC_OK;
+}
+
+
+pic_status pic_batch_workspace_bytes(int32_t precision, int32_t max_slots, size_t* bytes) {
+  if (!bytes || max_slots < 1 || max_slots > 1024 || (precision != PIC_FP32 && precision != PIC_FP64))
+    return fail(PIC_EINVAL, "bad batch size or precision");
+  *bytes = batch_layout(precision, max_slots, nullptr, nullptr);
+  return PIC_OK;
+}
+
+pic_status pic_batch_create(int32_t precision, int32_t max_slots, int32_t quantum,
+                            int64_t max_particles, int64_t max_cells, void* d_ws, size_t ws_bytes,
+                            void* stream, pic_batch** out) {
+  if (!out) return fail(PIC_EINVAL, "null output handle");
+  *out = nullptr;
+  size_t need = 0;
+  pic_status ps = pic_batch_workspace_bytes(precision, max_slots, &need);
+  if (ps) return ps;
+  if (!d_ws || reinterpret_cast<uintptr_t>(d_ws) % 256) return fail(PIC_EINVAL, "bad batch workspace");
+  if (ws_bytes < need) return fail(PIC_ENOMEM, "batch workspace too small");
+  if (quantum < 1 || max_particles < 0 || max_cells < 0) return fail(PIC_EINVAL, "bad batch limits");
+  if (!stream) return fail(PIC_EINVAL, "a batch needs a stream other than the null stream (graph capture)");
+  pic_batch* b = new pic_batch();
+  b->prec = precision;
+  b->max_slots = max_slots;
+  b->quantum = quantum;
+  b->slot_bytes = slot_bytes_for(precision);
+  batch_layout(precision, max_slots, b, static_cast<char*>(d_ws));
+  b->cap[0] = (int)(max_particles / kTile) + 2 * max_slots;
+  b->cap[1] = (int)((max_cells + 3ll * max_slots) / kFieldChunk) + 2 * max_slots;
+  b->cap[2] = (int)(max_particles / kSortTile) + 2 * max_slots;
+  b->runs.assign(max_slots, nullptr);
+  b->target.assign(max_slots, 0);
+  for (int k = 0; k < 3; ++k) b->nblk[k].assign(max_slots, 0);
+  hipStream_t st = S(stream);
+  hipError_t e = hipMemsetAsync(d_ws, 0, need - 256, st);
+  if (e != hipSuccess) {
+    delete b;
+    return fail(PIC_EHIP, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
+  }
+  for (int s = 0; s < max_slots && !ps; ++s)
+    ps = precision == PIC_FP32 ? write_slot<float>(b, s, st) : write_slot<double>(b, s, st);
+  if (!ps) ps = write_ranges(b, st);
+  if (ps) {
+    delete b;
+    return ps;
+  }
+  *out = b;
+  return PIC_OK;
+}
+
+pic_status pic_batch_admit(pic_batch* b, pic_run* r, int64_t n_steps, void* stream, int32_t* slot) {
+  if (!b || !r || !slot || n_steps < 0) return fail(PIC_EINVAL, "null batch, run or slot");
+  if (r->batch) return fail(PIC_EINVAL, "run is already in a batch");
+  if (r->d.prec != b->prec) return fail(PIC_EINVAL, "run precision differs from the batch");
+  if (r->step != 0 || r->pp != 0) return fail(PIC_EINVAL, "only runs at step 0 can join a batch");
+  if (r->cfg.sort_interval != b->quantum)
+    return fail(PIC_EINVAL, "run sort_interval must equal the batch quantum");
+  int free_slot = -1;
+  for (int s = 0; s < b->max_slots; ++s)
+    if (!b->runs[s]) {
+      free_slot = s;
+      break;
+    }
+  if (free_slot < 0) return fail(PIC_EBUSY, "no free batch slot");
+  const int need[3] = {tiles_for(r->n_max[0]) + tiles_for(r->n_max[1]), field_blocks_for(r),
+                       sort_blocks_for(r->n_max[0]) + sort_blocks_for(r->n_max[1])};
+  for (int k = 0; k < 3; ++k) {
+    long long used = 0;
+    for (int s = 0; s < b->max_slots; ++s) used += b->nblk[k][s];
+    if (used + need[k] > b->cap[k]) return fail(PIC_EBUSY, "batch work capacity exhausted");
+  }
+  b->runs[free_slot] = r;
+  b->target[free_slot] = n_steps;
+  for (int k = 0; k < 3; ++k) b->nblk[k][free_slot] = need[k];
+  hipStream_t st = S(stream);
+  pic_status ps = b->prec == PIC_FP32 ? write_slot<float>(b, free_slot, st) : write_slot<double>(b, free_slot, st);
+  if (!ps) ps = write_ranges(b, st);
+  if (ps) {
+    b->runs[free_slot] = nullptr;
+    for (int k = 0; k < 3; ++k) b->nblk[k][free_slot] = 0;
+    return ps;
+  }
+  r->batch = b;
+  *slot = free_slot;
+  return PIC_OK;
+}
+
+pic_status pic_batch_step(pic_batch* b, int32_t n_quanta, void* stream) {
+  if (!b || n_quanta < 0 || !stream) return fail(PIC_EINVAL, "null batch/stream or negative count");
+  hipStream_t st = S(stream);
+  if (!b->exec) {
+    pic_status ps = b->prec == PIC_FP32 ? capture_batch<float>(b, st) : capture_batch<double>(b, st);
+    if (ps) return ps;
+  }
+  for (int q = 0; q < n_quanta; ++q) HIP_TRY(hipGraphLaunch(b->exec, st));
+  return PIC_OK;
+}
+
+pic_status pic_batch_poll(pic_batch* b, int64_t* steps, void* stream) {
+  if (!b || !steps || !stream) return fail(PIC_EINVAL, "null batch, output or stream");
+  hipStream_t st = S(stream);
+  const size_t off = b->prec == PIC_FP32 ? offsetof(SlotDev<float>, step) : offsetof(SlotDev<double>, step);
+  hipLaunchKernelGGL(k_gather_steps, dim3((b->max_slots + 255) / 256), dim3(256), 0, st, b->tab,
+                     b->slot_bytes, off, b->max_slots, b->steps);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(steps, b->steps, b->max_slots * sizeof(long long), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  for (int s = 0; s < b->max_slots; ++s)
+    if (!b->runs[s]) steps[s] = -1;
+  return PIC_OK;
+}
+
+pic_status pic_batch_release(pic_batch* b, int32_t slot, void* stream) {
+  if (!b || slot < 0 || slot >= b->max_slots || !b->runs[slot]) return fail(PIC_EINVAL, "bad slot");
+  hipStream_t st = S(stream);
+  HIP_TRY(hipStreamSynchronize(st));
+  pic_run* r = b->runs[slot];
+  long long step = 0;
+  HIP_TRY(hipMemcpy(&step, r->step_dev, sizeof(step), hipMemcpyDeviceToHost));
+  r->step = step;
+  // sorts ran at the starts of steps K, 2K, ... below `step`
+  r->pp = step > 0 ? (int)(((step - 1) / r->cfg.sort_interval) & 1) : 0;
+  r->batch = nullptr;
+  b->runs[slot] = nullptr;
+  b->target[slot] = 0;
+  for (int k = 0; k < 3; ++k) b->nblk[k][slot] = 0;
+  pic_status ps = b->prec == PIC_FP32 ? write_slot<float>(b, slot, st) : write_slot<double>(b, slot, st);
+  if (!ps) ps = write_ranges(b, st);
+  return ps;
+}
+
+void pic_batch_free(pic_batch* b) {
+  if (!b) return;
+  for (int s = 0; s < b->max_slots; ++s)
+    if (b->runs[s]) b->runs[s]->batch = nullptr;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  delete b;
 }
 
 }  // extern "C"

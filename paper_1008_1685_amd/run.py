@@ -45,15 +45,23 @@ def _ptr(a):
 class Run:
     """One laser-foil run resident on the GPU."""
 
-    def __init__(self, cfg: dict, capacity: int = 0, device: str = "cuda", workspace=None):
+    def __init__(self, cfg: dict, capacity: int = 0, device: str = "cuda", workspace=None,
+                 stream=None):
+        """stream: a torch.cuda.Stream for every call of this run (default: the
+        current stream at each call)."""
         import torch
 
         self.lib = N.load()
+        self.stream = stream
         self.cfg = dict(cfg)
         self._c = make_config(cfg, capacity)
         self.ws_bytes = workspace_bytes(cfg, capacity)
         if workspace is None:
-            workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+            if stream is not None:
+                with torch.cuda.stream(stream):
+                    workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+            else:
+                workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
         elif workspace.numel() * workspace.element_size() < self.ws_bytes:
             raise ValueError("workspace tensor too small")
         self.ws = workspace
@@ -64,11 +72,11 @@ class Run:
         self.info = self.get_info()
         self.rdt = np.float32 if self.info["precision"] == N.PIC_FP32 else np.float64
 
-    @staticmethod
-    def _stream():
+    def _stream(self):
         import torch
 
-        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+        st = self.stream if self.stream is not None else torch.cuda.current_stream()
+        return C.c_void_p(st.cuda_stream)
 
     def close(self):
         if self._h:

@@ -1,0 +1,155 @@
+"""Serving form: continuous batching of independent laser-foil runs.
+
+``Batch`` wraps the C batch entry points (argument marshalling only).
+``Server`` is the request loop: requests arrive over wall-clock time, are
+admitted in arrival order while a batch slot and the device-memory budget
+allow, are advanced together one captured quantum at a time, and are
+retired (diagnostics, memory freed) as soon as they reach their step count.
+"""
+from __future__ import annotations
+
+import collections
+import ctypes as C
+import time
+
+import numpy as np
+
+from . import _native as N
+from .run import Run, workspace_bytes
+
+
+class Batch:
+    def __init__(self, precision: str = "fp32", max_slots: int = 64, quantum: int = 16,
+                 max_particles: int = 4 * 10 ** 7, max_cells: int = 10 ** 6, stream=None):
+        import torch
+
+        self.lib = N.load()
+        self.prec = N.PIC_FP64 if precision == "fp64" else N.PIC_FP32
+        self.max_slots, self.quantum = int(max_slots), int(quantum)
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        n = C.c_size_t()
+        N.check(self.lib.pic_batch_workspace_bytes(self.prec, self.max_slots, C.byref(n)),
+                "pic_batch_workspace_bytes")
+        with torch.cuda.stream(self.stream):
+            self.ws = torch.empty(n.value, dtype=torch.uint8, device="cuda")
+        self._h = C.c_void_p()
+        N.check(self.lib.pic_batch_create(self.prec, self.max_slots, self.quantum, int(max_particles),
+                                          int(max_cells), C.c_void_p(self.ws.data_ptr()),
+                                          C.c_size_t(n.value), self._st(), C.byref(self._h)),
+                "pic_batch_create")
+        self._steps = (C.c_int64 * self.max_slots)()
+
+    def _st(self):
+        return C.c_void_p(self.stream.cuda_stream)
+
+    def admit(self, run: Run, n_steps: int) -> int:
+        slot = C.c_int32(-1)
+        N.check(self.lib.pic_batch_admit(self._h, run._h, int(n_steps), self._st(), C.byref(slot)),
+                "pic_batch_admit")
+        return slot.value
+
+    def try_admit(self, run: Run, n_steps: int):
+        """Slot index, or None when no slot or work capacity is free."""
+        slot = C.c_int32(-1)
+        st = self.lib.pic_batch_admit(self._h, run._h, int(n_steps), self._st(), C.byref(slot))
+        if st == N.PIC_EBUSY:
+            return None
+        N.check(st, "pic_batch_admit")
+        return slot.value
+
+    def step(self, n_quanta: int = 1):
+        N.check(self.lib.pic_batch_step(self._h, int(n_quanta), self._st()), "pic_batch_step")
+
+    def poll(self) -> np.ndarray:
+        N.check(self.lib.pic_batch_poll(self._h, self._steps, self._st()), "pic_batch_poll")
+        return np.frombuffer(self._steps, dtype=np.int64).copy()
+
+    def release(self, slot: int):
+        N.check(self.lib.pic_batch_release(self._h, int(slot), self._st()), "pic_batch_release")
+
+    def close(self):
+        if self._h:
+            self.lib.pic_batch_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def run_steps(cfg: dict) -> int:
+    """Steps of a request: its periods at dt = cfl dx, dx = lambda / cells_per_lambda."""
+    return int(round(cfg["periods"] * cfg["cells_per_lambda"] / cfg["cfl"]))
+
+
+class Server:
+    """Continuous-batching request loop over one Batch.
+
+    budget_bytes bounds the summed run workspaces resident at once;
+    quanta_per_poll is how many captured quanta are enqueued between two
+    checks for finished runs."""
+
+    def __init__(self, budget_bytes: int, max_slots: int = 64, quantum: int = 16,
+                 max_particles: int = 4 * 10 ** 7, max_cells: int = 2 * 10 ** 6,
+                 quanta_per_poll: int = 2, precision: str = "fp32"):
+        self.budget = int(budget_bytes)
+        self.batch = Batch(precision, max_slots, quantum, max_particles, max_cells)
+        self.quanta_per_poll = int(quanta_per_poll)
+        self.peak_bytes = 0
+
+    def serve(self, requests, keep_runs: bool = False, clock=time.perf_counter):
+        """requests: list of dict(arrival=seconds, cfg=...), sorted by arrival.
+        Returns one record per request: arrival, admitted, done, latency
+        (seconds, wall clock from the start of serve), steps, particles and
+        final diagnostics (and the Run itself with keep_runs)."""
+        b = self.batch
+        pending = collections.deque(sorted(requests, key=lambda r: r["arrival"]))
+        queue = collections.deque()
+        active = {}
+        used = 0
+        out = []
+        t0 = clock()
+        while pending or queue or active:
+            now = clock() - t0
+            while pending and pending[0]["arrival"] <= now:
+                queue.append(pending.popleft())
+            while queue:
+                req = queue[0]
+                need = workspace_bytes(req["cfg"])
+                if used + need > self.budget and active:
+                    break
+                run = Run(req["cfg"], stream=b.stream)
+                steps = run_steps(req["cfg"])
+                slot = b.try_admit(run, steps)
+                if slot is None:
+                    run.close()
+                    break
+                queue.popleft()
+                used += need
+                self.peak_bytes = max(self.peak_bytes, used)
+                active[slot] = dict(req=req, run=run, steps=steps, need=need,
+                                    admitted=clock() - t0)
+            if not active:
+                if pending:
+                    time.sleep(max(0.0, pending[0]["arrival"] - (clock() - t0)))
+                continue
+            b.step(self.quanta_per_poll)
+            steps_now = b.poll()
+            t_done = clock() - t0
+            for slot in [s for s, a in active.items() if steps_now[s] >= a["steps"]]:
+                a = active.pop(slot)
+                b.release(slot)
+                d = a["run"].diag(allow_nonfinite=True)
+                rec = dict(name=a["req"]["cfg"].get("name", ""), arrival=a["req"]["arrival"],
+                           admitted=a["admitted"], done=t_done,
+                           latency=t_done - a["req"]["arrival"], steps=a["steps"],
+                           particles=int(sum(a["run"].info["n_init"])), diag=d)
+                if keep_runs:
+                    rec["run"] = a["run"]
+                else:
+                    a["run"].close()
+                out.append(rec)
+                used -= a["need"]
+        return out

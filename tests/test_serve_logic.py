@@ -1,0 +1,106 @@
+"""Host logic of the serving loop (no GPU): admission order, device-memory
+budget, slot capacity and reuse, completion bookkeeping.  The batch and
+runs are replaced by stand-ins that count steps like the device does."""
+import numpy as np
+import pytest
+
+import paper_1008_1685_amd.serve as S
+from workloads import poisson_stream, preset
+
+
+class FakeRun:
+    def __init__(self, cfg, stream=None, **kw):
+        self.cfg = cfg
+        self.info = dict(n_init=(10, 10))
+        self._h = object()
+        self.closed = False
+
+    def diag(self, allow_nonfinite=False):
+        return dict(step=self.step, gauss_int=0)
+
+    def close(self):
+        self.closed = True
+
+
+class FakeBatch:
+    def __init__(self, precision, max_slots, quantum, max_particles, max_cells):
+        self.max_slots, self.quantum = max_slots, quantum
+        self.slots = [None] * max_slots
+        self.stream = None
+        self.admitted = []
+
+    def try_admit(self, run, n_steps):
+        for i, s in enumerate(self.slots):
+            if s is None:
+                run.step, run.target = 0, n_steps
+                self.slots[i] = run
+                self.admitted.append(run.cfg["name"])
+                return i
+        return None
+
+    def step(self, n):
+        for r in self.slots:
+            if r is not None:
+                r.step = min(r.target, r.step + n * self.quantum)
+
+    def poll(self):
+        return np.array([-1 if r is None else r.step for r in self.slots], np.int64)
+
+    def release(self, slot):
+        self.slots[slot] = None
+
+
+@pytest.fixture
+def fakes(monkeypatch):
+    monkeypatch.setattr(S, "Run", FakeRun)
+    monkeypatch.setattr(S, "Batch", FakeBatch)
+    sizes = {}
+    monkeypatch.setattr(S, "workspace_bytes", lambda cfg, capacity=0: sizes.get(cfg["name"], 100))
+    return sizes
+
+
+def _reqs(n, steps_periods=(1.0, 2.0, 3.0)):
+    out = []
+    for i in range(n):
+        cfg = dict(preset("c1", periods=steps_periods[i % len(steps_periods)]), name=f"r{i}")
+        out.append(dict(arrival=0.0, cfg=cfg))
+    return out
+
+
+def test_every_request_completes_in_arrival_order_of_admission(fakes):
+    srv = S.Server(budget_bytes=10 ** 9, max_slots=2)
+    reqs = _reqs(5)
+    recs = srv.serve(reqs)
+    assert sorted(r["name"] for r in recs) == [f"r{i}" for i in range(5)]
+    assert srv.batch.admitted == [f"r{i}" for i in range(5)]
+    for r in recs:
+        assert r["diag"]["step"] == r["steps"] == S.run_steps(reqs[int(r["name"][1:])]["cfg"])
+        assert r["done"] >= r["admitted"] >= r["arrival"]
+
+
+def test_memory_budget_bounds_resident_runs(fakes):
+    for i in range(6):
+        fakes[f"r{i}"] = 400
+    srv = S.Server(budget_bytes=1000, max_slots=8)
+    recs = srv.serve(_reqs(6))
+    assert len(recs) == 6
+    assert srv.peak_bytes <= 1000 and srv.peak_bytes == 800
+
+
+def test_a_run_larger_than_the_budget_runs_alone(fakes):
+    fakes["r0"] = 5000
+    srv = S.Server(budget_bytes=1000, max_slots=8)
+    recs = srv.serve(_reqs(3))
+    assert len(recs) == 3
+    assert srv.peak_bytes == 5000  # admitted only into an empty batch
+
+
+def test_poisson_stream_shape():
+    runs = poisson_stream(0, n_runs=256, rate=20.0)
+    t = np.array([r["arrival"] for r in runs])
+    assert np.all(np.diff(t) > 0)
+    assert 256 / t[-1] == pytest.approx(20.0, rel=0.2)
+    n = np.array([2 * r["cfg"]["ppc"] * round(r["cfg"]["thickness"] * 100) for r in runs])
+    assert n.min() >= 0.9e4 and n.max() <= 1.1e6
+    assert {r["cfg"]["pol"] for r in runs} == {"LP", "CP"}
+    assert all(30 <= r["cfg"]["periods"] <= 80 for r in runs)
