@@ -25,6 +25,16 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 
 
+def kernel_hash() -> str:
+    """SHA-256 of the device source the push kernel is built from."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("kernels.hpp", "pic_lib.hip"):
+        h.update(open(os.path.join(ROOT, "paper_1008_1685_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
 def alg_bytes_per_push(precision: str, compensated: bool, rr: bool):
     """Algorithmic HBM bytes of one push (electron, ion): read cell, offset,
     3 momenta, weight; write cell, offset, 3 momenta; compensated RR also
@@ -114,6 +124,33 @@ def serve_bench(n_runs=256, rate=20.0, seed=0, max_slots=64, budget_gb=64.0):
                 peak_resident_bytes=srv.peak_bytes, max_slots=max_slots, failed_checks=bad)
 
 
+def write_traffic(fetch, write, cfetch, cwrite, out_path):
+    """profiles/traffic.json from rocprofv3 counter_collection.csv files:
+    FETCH_SIZE and WRITE_SIZE of this benchmark (--steps 50 --warmup 3550
+    --no-side-runs --no-serve) and of a plain 1 GiB device copy
+    (torch b.copy_(a), the calibration of bytes reported per byte moved)."""
+    import csv
+
+    import numpy as np
+
+    def kib(path, name, last=50):
+        rows = [r for r in csv.DictReader(open(path)) if name in r["Kernel_Name"]]
+        return float(np.mean([float(r["Counter_Value"]) for r in rows][-last:])), len(rows)
+
+    f_copy, _ = kib(cfetch, "copyBuffer")
+    w_copy, _ = kib(cwrite, "copyBuffer")
+    f_factor, w_factor = 2 ** 30 / (f_copy * 1024), 2 ** 30 / (w_copy * 1024)
+    f_push, nf = kib(fetch, "k_push")
+    w_push, nw = kib(write, "k_push")
+    out = dict(workload="c3", kernel="k_push", kernel_sha256=kernel_hash(),
+               fetch_kib=f_push, write_kib=w_push, fetch_factor=f_factor, write_factor=w_factor,
+               read_bytes=f_push * 1024 * f_factor, write_bytes=w_push * 1024 * w_factor,
+               bytes_per_launch=f_push * 1024 * f_factor + w_push * 1024 * w_factor,
+               launches_averaged=min(50, nf, nw))
+    json.dump(out, open(out_path, "w"), indent=1)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -124,8 +161,16 @@ def main():
     ap.add_argument("--no-side-runs", action="store_true",
                     help="skip the RR-off and FP64 comparison runs and the CPU baseline")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-form measurement")
+    ap.add_argument("--serve-only", type=int, default=0, metavar="N",
+                    help="only run the serving measurement, on the first N requests")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    ap.add_argument("--write-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
+                                                         "COPY_WRITE_CSV"),
+                    help="write --traffic-json from rocprofv3 counter files and exit")
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(*args.write_traffic, args.traffic_json)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU particle decomposition is a design note, not built)", flush=True)
@@ -136,6 +181,9 @@ def main():
     from workloads import preset
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.serve_only:
+        print(json.dumps(dict(serving=serve_bench(n_runs=args.serve_only))), flush=True)
+        return
     cfg = preset(args.workload)
     res = time_run(cfg, args.steps, args.warmup, args.diag_every)
     pushes = (res["n_e"] + res["n_i"]) * args.steps
@@ -145,11 +193,13 @@ def main():
     avg_push_s = push_ms * 1e-3 / max(push_n, 1)
     bytes_per_launch = be * res["n_e"] + bi * res["n_i"]
     achieved = bytes_per_launch / avg_push_s / 1e9
+    # HBM bytes per push launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (calibrated
+    # on a plain copy); only valid for the kernel source the counters were taken on
     traffic = None
     if os.path.exists(args.traffic_json):
         try:
             tj = json.load(open(args.traffic_json))
-            if tj.get("workload") == args.workload:
+            if tj.get("workload") == args.workload and tj.get("kernel_sha256") == kernel_hash():
                 traffic = tj.get("bytes_per_launch")
         except Exception:
             traffic = None

@@ -27,6 +27,9 @@ namespace pic {
 #ifndef PIC_PUSH_PPT
 #define PIC_PUSH_PPT 16
 #endif
+#ifndef PIC_BATCH_PPT
+#define PIC_BATCH_PPT 4
+#endif
 #ifndef PIC_PUSH_LDS_SLOTS
 #define PIC_PUSH_LDS_SLOTS 3072
 #endif
@@ -42,8 +45,13 @@ namespace pic {
 
 constexpr int kDead = INT_MIN;        // cell index of a removed particle
 constexpr int kThreads = 256;         // push work-group
-constexpr int kPPT = PIC_PUSH_PPT;    // particles per thread per tile
+constexpr int kPPT = PIC_PUSH_PPT;    // particles per thread per tile (single runs)
 constexpr int kTile = kThreads * kPPT;
+// Batched runs are small and many: a shorter tile lowers the latency of a
+// step of one run (the window set-up and flush are paid over fewer pushes).
+constexpr int kBatchPPT = PIC_BATCH_PPT;
+constexpr int kBatchTile = kThreads * kBatchPPT;
+constexpr int kMinTile = kTile < kBatchTile ? kTile : kBatchTile;
 constexpr int kLdsSlots = PIC_PUSH_LDS_SLOTS;  // 64-bit LDS current accumulators per work-group
 constexpr int kUnroll = PIC_PUSH_UNROLL;      // push loop unroll
 constexpr int kLanes = 64;            // wavefront width
@@ -257,7 +265,7 @@ __device__ __forceinline__ void deposit(DepositCtx& d, int c, R o, int c1, R o1,
   }
 }
 
-// per-thread partial sums (a thread pushes kPPT particles; FP64 from the
+// per-thread partial sums (a thread pushes the PPT particles of its tile; FP64 from the
 // work-group sum on)
 struct PushAcc {
   float rad, esc, stiff;
@@ -408,7 +416,7 @@ __device__ __forceinline__ void push_particle(const PushArgs<R>& a, const Specie
   }
 }
 
-template <typename R, bool RR, bool COMP>
+template <typename R, bool RR, bool COMP, int PPT>
 __device__ __forceinline__ void push_tile(const PushArgs<R>& a, int s, int tile, int n, int base,
                                           unsigned long long* lds) {
   __shared__ int s_mn[kThreads / kLanes], s_mx[kThreads / kLanes];
@@ -417,10 +425,10 @@ __device__ __forceinline__ void push_tile(const PushArgs<R>& a, int s, int tile,
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
 
   // cells of this thread's particles and the tile's cell range
-  int cl[kPPT];
+  int cl[PPT];
   int cmin = INT_MAX, cmax = INT_MIN;
 #pragma unroll
-  for (int k = 0; k < kPPT; ++k) {
+  for (int k = 0; k < PPT; ++k) {
     const int i = base + k * kThreads + tid;
     cl[k] = i < n ? ld(sp.cell, (unsigned)i) : kDead;
     if (cl[k] != kDead) {
@@ -466,16 +474,16 @@ __device__ __forceinline__ void push_tile(const PushArgs<R>& a, int s, int tile,
 #if PIC_PUSH_PREFETCH
   // the next particle's loads are in flight while this one is computed
 #pragma unroll kUnroll
-  for (int k = 0; k < kPPT; ++k) {
+  for (int k = 0; k < PPT; ++k) {
     const int i = base + k * kThreads + tid;
     PData<R> nxt{};
-    if (k + 1 < kPPT) nxt = load_particle<R, COMP>(sp, i + kThreads, cl[k + 1]);
+    if (k + 1 < PPT) nxt = load_particle<R, COMP>(sp, i + kThreads, cl[k + 1]);
     push_particle<R, RR, COMP>(a, sp, s, i, cl[k], cur, dc, acc);
     cur = nxt;
   }
 #else
 #pragma unroll kUnroll
-  for (int k = 0; k < kPPT; ++k) {
+  for (int k = 0; k < PPT; ++k) {
     const int i = base + k * kThreads + tid;
     const PData<R> pd = load_particle<R, COMP>(sp, i, cl[k]);
     push_particle<R, RR, COMP>(a, sp, s, i, cl[k], pd, dc, acc);
@@ -520,21 +528,21 @@ __device__ __forceinline__ void push_tile(const PushArgs<R>& a, int s, int tile,
   }
 }
 
-template <typename R>
+template <typename R, int PPT>
 __device__ __forceinline__ void push_one_tile(const PushArgs<R>& a, int tile,
                                               unsigned long long* lds) {
   const int s = tile < a.tiles0 ? 0 : 1;
   const int tl = s ? tile - a.tiles0 : tile;
   const int n = (int)a.count[s];
-  const int base = tl * kTile;
+  const int base = tl * (kThreads * PPT);
   if (base >= n) return;
   if (s == 0 && a.rr0) {
     if (a.comp)
-      push_tile<R, true, true>(a, s, tile, n, base, lds);
+      push_tile<R, true, true, PPT>(a, s, tile, n, base, lds);
     else
-      push_tile<R, true, false>(a, s, tile, n, base, lds);
+      push_tile<R, true, false, PPT>(a, s, tile, n, base, lds);
   } else {
-    push_tile<R, false, false>(a, s, tile, n, base, lds);
+    push_tile<R, false, false, PPT>(a, s, tile, n, base, lds);
   }
 }
 
@@ -548,7 +556,7 @@ __device__ __forceinline__ void push_one_tile(const PushArgs<R>& a, int tile,
 template <typename R>
 __global__ PIC_PUSH_BOUNDS void k_push(PushArgs<R> a) {
   __shared__ unsigned long long lds[kLdsSlots];
-  push_one_tile(a, (int)blockIdx.x, lds);
+  push_one_tile<R, kPPT>(a, (int)blockIdx.x, lds);
 }
 
 // ---------------------------------------------------------------- fields
@@ -937,82 +945,119 @@ struct SlotDev {
   int nx;
 };
 
-// slot whose work range [start[s], start[s + 1]) holds block b
-__device__ __forceinline__ int find_slot(const int* start, int n, int b) {
-  int lo = 0, hi = n;
-  while (hi - lo > 1) {
-    const int m = (lo + hi) >> 1;
-    if (start[m] <= b)
-      lo = m;
-    else
-      hi = m;
-  }
-  return lo;
+constexpr int kMaxSlots = 1024;
+
+// A value the whole wave shares, moved to scalar registers.
+__device__ __forceinline__ long long uniform(long long v) {
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(v & 0xffffffffll));
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)((unsigned long long)v >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
 }
 
+// Work ranges of the slots, copied to LDS once per work-group; slot(b) is
+// the slot whose range [start[s], start[s + 1]) holds work item b.
+struct SlotRanges {
+  int* st;  // LDS, n + 1 entries
+  int n;
+  // b is block-uniform, so is the result: readfirstlane lets the compiler
+  // keep the slot (and every argument loaded through it) in scalar registers
+  __device__ __forceinline__ int slot(int b) const {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+      const int m = (lo + hi) >> 1;
+      if (st[m] <= b)
+        lo = m;
+      else
+        hi = m;
+    }
+    return __builtin_amdgcn_readfirstlane(lo);
+  }
+  __device__ __forceinline__ int first(int sl) const { return __builtin_amdgcn_readfirstlane(st[sl]); }
+  __device__ __forceinline__ int total() const { return __builtin_amdgcn_readfirstlane(st[n]); }
+};
+
+__device__ __forceinline__ SlotRanges load_ranges(const int* start, int n, int* lds) {
+  for (int i = threadIdx.x; i <= n; i += blockDim.x) lds[i] = start[i];
+  __syncthreads();
+  return SlotRanges{lds, n};
+}
+
+// Batched push and field launches run one work-group per work item: the host
+// sets their grids to the resident total whenever the slot table changes (a
+// grid-stride loop here would keep more values live and cost occupancy).
 template <typename R>
-__global__ PIC_PUSH_BOUNDS void k_push_batch(const SlotDev<R>* slots, const int* start, int n) {
+__global__ PIC_PUSH_BOUNDS void k_push_batch(const SlotDev<R>* __restrict__ slots, const int* __restrict__ start, int n) {
   __shared__ unsigned long long lds[kLdsSlots];
+  __shared__ int rng[kMaxSlots + 1];
+  const SlotRanges sr = load_ranges(start, n, rng);
   const int b = (int)blockIdx.x;
-  if (b >= start[n]) return;
-  const int sl = find_slot(start, n, b);
+  if (b >= sr.total()) return;
+  const int sl = sr.slot(b);
   const SlotDev<R>& S = slots[sl];
-  const long long st = *S.step;
+  const long long st = uniform(*S.step);
   if (st >= S.target) return;
   const int pp = (int)((st / S.sort_interval) & 1), fp = (int)(st & 1);
-  push_one_tile<R>(S.push[pp][fp], b - start[sl], lds);
+  push_one_tile<R, kBatchPPT>(S.push[pp][fp], b - sr.first(sl), lds);
 }
 
 template <typename R>
-__global__ __launch_bounds__(kFieldChunk) void k_field_batch(const SlotDev<R>* slots,
-                                                            const int* start, int n) {
+__global__ __launch_bounds__(kFieldChunk) void k_field_batch(const SlotDev<R>* __restrict__ slots,
+                                                            const int* __restrict__ start, int n) {
+  __shared__ int rng[kMaxSlots + 1];
+  const SlotRanges sr = load_ranges(start, n, rng);
   const int b = (int)blockIdx.x;
-  if (b >= start[n]) return;
-  const int sl = find_slot(start, n, b);
+  if (b >= sr.total()) return;
+  const int sl = sr.slot(b);
   const SlotDev<R>& S = slots[sl];
-  const long long st = *S.step;
+  const long long st = uniform(*S.step);
   if (st >= S.target) return;
-  field_chunk<R>(S.field[st & 1], b - start[sl]);
+  field_chunk<R>(S.field[st & 1], b - sr.first(sl));
 }
 
 template <typename R>
 __device__ __forceinline__ bool sort_due(const SlotDev<R>& S, int* q) {
-  const long long st = *S.step;
+  const long long st = uniform(*S.step);
   if (st >= S.target || st <= 0 || st % S.sort_interval) return false;
   *q = (int)((st / S.sort_interval - 1) & 1);
   return true;
 }
 
 template <typename R>
-__global__ __launch_bounds__(kSortThreads) void k_sort_hist_batch(const SlotDev<R>* slots,
-                                                                 const int* start, int n) {
-  const int b = (int)blockIdx.x;
-  if (b >= start[n]) return;
-  const int sl = find_slot(start, n, b);
-  int q;
-  if (!sort_due(slots[sl], &q)) return;
-  sort_hist_block<R>(slots[sl].sort[q], b - start[sl]);
+__global__ __launch_bounds__(kSortThreads) void k_sort_hist_batch(const SlotDev<R>* __restrict__ slots,
+                                                                 const int* __restrict__ start, int n) {
+  __shared__ int rng[kMaxSlots + 1];
+  const SlotRanges sr = load_ranges(start, n, rng);
+  for (int b = (int)blockIdx.x; b < sr.total(); b += (int)gridDim.x) {
+    const int sl = sr.slot(b);
+    int q;
+    if (!sort_due(slots[sl], &q)) continue;
+    sort_hist_block<R>(slots[sl].sort[q], b - sr.first(sl));
+  }
 }
 
 template <typename R>
 __global__ __launch_bounds__(1024) void k_sort_scan_batch(const SlotDev<R>* slots, int n) {
-  const int sl = (int)blockIdx.x >> 1, sp = (int)blockIdx.x & 1;
-  if (sl >= n) return;
-  const SlotDev<R>& S = slots[sl];
-  int q;
-  if (!sort_due(S, &q)) return;
-  sort_scan_species(S.cnt[sp], S.cur[sp], S.count + 2 * (q ^ 1) + sp, S.nx);
+  for (int w = (int)blockIdx.x; w < 2 * n; w += (int)gridDim.x) {
+    const int sl = w >> 1, sp = w & 1;
+    const SlotDev<R>& S = slots[sl];
+    int q;
+    if (!sort_due(S, &q)) continue;
+    __syncthreads();
+    sort_scan_species(S.cnt[sp], S.cur[sp], S.count + 2 * (q ^ 1) + sp, S.nx);
+  }
 }
 
 template <typename R>
-__global__ __launch_bounds__(kSortThreads) void k_sort_scatter_batch(const SlotDev<R>* slots,
-                                                                    const int* start, int n) {
-  const int b = (int)blockIdx.x;
-  if (b >= start[n]) return;
-  const int sl = find_slot(start, n, b);
-  int q;
-  if (!sort_due(slots[sl], &q)) return;
-  sort_scatter_block<R>(slots[sl].sort[q], b - start[sl]);
+__global__ __launch_bounds__(kSortThreads) void k_sort_scatter_batch(const SlotDev<R>* __restrict__ slots,
+                                                                    const int* __restrict__ start, int n) {
+  __shared__ int rng[kMaxSlots + 1];
+  const SlotRanges sr = load_ranges(start, n, rng);
+  for (int b = (int)blockIdx.x; b < sr.total(); b += (int)gridDim.x) {
+    const int sl = sr.slot(b);
+    int q;
+    if (!sort_due(slots[sl], &q)) continue;
+    sort_scatter_block<R>(slots[sl].sort[q], b - sr.first(sl));
+  }
 }
 
 template <typename R>

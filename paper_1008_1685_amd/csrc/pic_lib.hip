@@ -90,7 +90,7 @@ pic_status derive(const pic_config* c, Derived* d) {
   d->cap = std::max<long long>(d->n_foil, c->capacity);
   // kernels address particle arrays with 32-bit byte offsets
   const long long elem = c->precision == PIC_FP32 ? 4 : 8;
-  if (d->cap < 0 || d->cap * elem > (1ll << 32) - (long long)kTile * elem)
+  if (d->cap < 0 || d->cap * elem > (1ll << 32) - (long long)std::max(kTile, kBatchTile) * elem)
     return fail(PIC_EINVAL, "capacity per species too large (arrays must stay below 4 GiB)");
   d->prec = c->precision;
   d->rsize = c->precision == PIC_FP32 ? sizeof(float) : sizeof(double);
@@ -153,7 +153,7 @@ struct pic_run {
 
 namespace {
 
-int tiles_for(long long n) { return (int)((n + kTile - 1) / kTile); }
+int tiles_for(long long n, int tile = kTile) { return (int)((n + tile - 1) / tile); }
 
 void carve(pic_run* r, Carver& cv) {
   const Derived& d = r->d;
@@ -185,7 +185,7 @@ void carve(pic_run* r, Carver& cv) {
   r->count = cv.take<long long>(4);
   r->step_dev = cv.take<long long>(1);
   r->flags = cv.take<int>(4);
-  r->tiles_max = 2 * tiles_for(d.cap);
+  r->tiles_max = 2 * tiles_for(d.cap, kMinTile);  // a run may also step in a batch
   r->acc = cv.take<double>(4 * (size_t)std::max(r->tiles_max, 1));
   r->budget = cv.take<double>(4);
   for (int s = 0; s < 2; ++s) {
@@ -260,12 +260,12 @@ int sort_blocks_for(long long n) {
 
 // Kernel arguments of run r for particle buffer parity pp and field parity fp.
 template <typename R>
-PushArgs<R> make_push_args(const pic_run* r, int pp, int fp) {
+PushArgs<R> make_push_args(const pic_run* r, int pp, int fp, int tile = kTile) {
   const Derived& d = r->d;
   PushArgs<R> a{};
   for (int s = 0; s < 2; ++s) a.sp[s] = dev<R>(r->sp[s][pp]);
   a.count = r->count + 2 * pp;
-  a.tiles0 = tiles_for(r->n_max[0]);
+  a.tiles0 = tiles_for(r->n_max[0], tile);
   a.f = fdev<R>(r, fp);
   for (int k = 0; k < 3; ++k) a.J[k] = r->J[fp][k];
   a.acc = r->acc;
@@ -285,7 +285,7 @@ PushArgs<R> make_push_args(const pic_run* r, int pp, int fp) {
   a.sw = (R)(256.0 / d.w_ref);
   for (int s = 0; s < 2; ++s)  // the kernel's own rounding of a particle of weight w_ref
     a.qw_ref[s] = a.Z[s] * (int)std::rint((R)d.w_ref * a.sw);
-  a.ntiles = a.tiles0 + tiles_for(r->n_max[1]);
+  a.ntiles = a.tiles0 + tiles_for(r->n_max[1], tile);
   return a;
 }
 
@@ -494,6 +494,9 @@ struct pic_batch {
   std::vector<int> nblk[3];
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // captured kernel nodes whose grid follows the resident work: kind 0 push,
+  // 1 field, 2 sort (hist and scatter)
+  std::vector<std::pair<hipGraphNode_t, int>> nodes;
 };
 
 namespace {
@@ -524,7 +527,7 @@ SlotDev<R> make_slot(const pic_batch* b, const pic_run* r, long long target) {
     return e;
   }
   for (int pp = 0; pp < 2; ++pp)
-    for (int fp = 0; fp < 2; ++fp) e.push[pp][fp] = make_push_args<R>(r, pp, fp);
+    for (int fp = 0; fp < 2; ++fp) e.push[pp][fp] = make_push_args<R>(r, pp, fp, kBatchTile);
   for (int fp = 0; fp < 2; ++fp) e.field[fp] = make_field_args<R>(r, fp, 0);
   for (int q = 0; q < 2; ++q) e.sort[q] = make_sort_args<R>(r, q);
   for (int s = 0; s < 2; ++s) {
@@ -547,6 +550,8 @@ pic_status write_slot(pic_batch* b, int slot, hipStream_t st) {
   return PIC_OK;
 }
 
+pic_status update_batch_grids(pic_batch* b);
+
 pic_status write_ranges(pic_batch* b, hipStream_t st) {
   std::vector<int> h((size_t)3 * (b->max_slots + 1));
   for (int k = 0; k < 3; ++k) {
@@ -556,27 +561,69 @@ pic_status write_ranges(pic_batch* b, hipStream_t st) {
     HIP_TRY(hipMemcpyAsync(b->start[k], o, (b->max_slots + 1) * sizeof(int), hipMemcpyHostToDevice, st));
   }
   HIP_TRY(hipStreamSynchronize(st));
-  return PIC_OK;
+  return update_batch_grids(b);
+}
+
+int batch_work(const pic_batch* b, int kind) {
+  long long t = 0;
+  for (int s = 0; s < b->max_slots; ++s) t += b->nblk[kind][s];
+  return (int)std::max<long long>(1, t);
 }
 
 template <typename R>
 pic_status capture_batch(pic_batch* b, hipStream_t st) {
   const SlotDev<R>* tab = reinterpret_cast<const SlotDev<R>*>(b->tab);
   const int n = b->max_slots;
+  int dev = 0, cus = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
   // every admitted run is at a multiple of the quantum here, so the sort
-  // (when due) is the first stage of the quantum
-  hipLaunchKernelGGL(k_sort_hist_batch<R>, dim3(b->cap[2]), dim3(kSortThreads), 0, st, tab, b->start[2], n);
-  hipLaunchKernelGGL(k_sort_scan_batch<R>, dim3(2 * n), dim3(1024), 0, st, tab, n);
-  hipLaunchKernelGGL(k_sort_scatter_batch<R>, dim3(b->cap[2]), dim3(kSortThreads), 0, st, tab, b->start[2], n);
+  // (when due) is the first stage of the quantum; grids are set to the
+  // resident work (one work-group per tile) by update_batch_grids
+  hipLaunchKernelGGL(k_sort_hist_batch<R>, dim3(1), dim3(kSortThreads), 0, st, tab, b->start[2], n);
+  hipLaunchKernelGGL(k_sort_scan_batch<R>, dim3(std::min(2 * n, cus)), dim3(1024), 0, st, tab, n);
+  hipLaunchKernelGGL(k_sort_scatter_batch<R>, dim3(1), dim3(kSortThreads), 0, st, tab, b->start[2], n);
   for (int q = 0; q < b->quantum; ++q) {
-    hipLaunchKernelGGL(k_push_batch<R>, dim3(b->cap[0]), dim3(kThreads), 0, st, tab, b->start[0], n);
-    hipLaunchKernelGGL(k_field_batch<R>, dim3(b->cap[1]), dim3(kFieldChunk), 0, st, tab, b->start[1], n);
+    hipLaunchKernelGGL(k_push_batch<R>, dim3(1), dim3(kThreads), 0, st, tab, b->start[0], n);
+    hipLaunchKernelGGL(k_field_batch<R>, dim3(1), dim3(kFieldChunk), 0, st, tab, b->start[1], n);
     hipLaunchKernelGGL(k_tick_batch<R>, dim3((n + 255) / 256), dim3(256), 0, st, tab, n);
   }
   hipError_t e = hipStreamEndCapture(st, &b->graph);
   if (e != hipSuccess) return fail(PIC_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
   HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  // remember the nodes whose grid follows the work
+  size_t num = 0;
+  HIP_TRY(hipGraphGetNodes(b->graph, nullptr, &num));
+  std::vector<hipGraphNode_t> all(num);
+  HIP_TRY(hipGraphGetNodes(b->graph, all.data(), &num));
+  const void* fpush = reinterpret_cast<const void*>(&k_push_batch<R>);
+  const void* ffield = reinterpret_cast<const void*>(&k_field_batch<R>);
+  const void* fhist = reinterpret_cast<const void*>(&k_sort_hist_batch<R>);
+  const void* fscat = reinterpret_cast<const void*>(&k_sort_scatter_batch<R>);
+  b->nodes.clear();
+  for (hipGraphNode_t nd : all) {
+    hipGraphNodeType ty;
+    HIP_TRY(hipGraphNodeGetType(nd, &ty));
+    if (ty != hipGraphNodeTypeKernel) continue;
+    hipKernelNodeParams kp{};
+    HIP_TRY(hipGraphKernelNodeGetParams(nd, &kp));
+    const int kind = kp.func == fpush ? 0 : kp.func == ffield ? 1 : (kp.func == fhist || kp.func == fscat) ? 2 : -1;
+    if (kind >= 0) b->nodes.emplace_back(nd, kind);
+  }
+  return PIC_OK;
+}
+
+// Set the grids of the captured launches to the resident work.
+pic_status update_batch_grids(pic_batch* b) {
+  if (!b->exec) return PIC_OK;
+  const int work[3] = {batch_work(b, 0), batch_work(b, 1), batch_work(b, 2)};
+  for (auto& nk : b->nodes) {
+    hipKernelNodeParams kp{};
+    HIP_TRY(hipGraphKernelNodeGetParams(nk.first, &kp));
+    kp.gridDim = dim3(work[nk.second]);
+    HIP_TRY(hipGraphExecKernelNodeSetParams(b->exec, nk.first, &kp));
+  }
   return PIC_OK;
 }
 
@@ -897,7 +944,7 @@ pic_status pic_timing_read(pic_run* r, double ms[3], int64_t launches[3], void* 
 
 
 pic_status pic_batch_workspace_bytes(int32_t precision, int32_t max_slots, size_t* bytes) {
-  if (!bytes || max_slots < 1 || max_slots > 1024 || (precision != PIC_FP32 && precision != PIC_FP64))
+  if (!bytes || max_slots < 1 || max_slots > kMaxSlots || (precision != PIC_FP32 && precision != PIC_FP64))
     return fail(PIC_EINVAL, "bad batch size or precision");
   *bytes = batch_layout(precision, max_slots, nullptr, nullptr);
   return PIC_OK;
@@ -921,7 +968,7 @@ pic_status pic_batch_create(int32_t precision, int32_t max_slots, int32_t quantu
   b->quantum = quantum;
   b->slot_bytes = slot_bytes_for(precision);
   batch_layout(precision, max_slots, b, static_cast<char*>(d_ws));
-  b->cap[0] = (int)(max_particles / kTile) + 2 * max_slots;
+  b->cap[0] = (int)(max_particles / kBatchTile) + 2 * max_slots;
   b->cap[1] = (int)((max_cells + 3ll * max_slots) / kFieldChunk) + 2 * max_slots;
   b->cap[2] = (int)(max_particles / kSortTile) + 2 * max_slots;
   b->runs.assign(max_slots, nullptr);
@@ -958,7 +1005,7 @@ pic_status pic_batch_admit(pic_batch* b, pic_run* r, int64_t n_steps, void* stre
       break;
     }
   if (free_slot < 0) return fail(PIC_EBUSY, "no free batch slot");
-  const int need[3] = {tiles_for(r->n_max[0]) + tiles_for(r->n_max[1]), field_blocks_for(r),
+  const int need[3] = {tiles_for(r->n_max[0], kBatchTile) + tiles_for(r->n_max[1], kBatchTile), field_blocks_for(r),
                        sort_blocks_for(r->n_max[0]) + sort_blocks_for(r->n_max[1])};
   for (int k = 0; k < 3; ++k) {
     long long used = 0;
@@ -986,6 +1033,7 @@ pic_status pic_batch_step(pic_batch* b, int32_t n_quanta, void* stream) {
   hipStream_t st = S(stream);
   if (!b->exec) {
     pic_status ps = b->prec == PIC_FP32 ? capture_batch<float>(b, st) : capture_batch<double>(b, st);
+    if (!ps) ps = update_batch_grids(b);
     if (ps) return ps;
   }
   for (int q = 0; q < n_quanta; ++q) HIP_TRY(hipGraphLaunch(b->exec, st));
