@@ -33,12 +33,10 @@ namespace pic {
 #ifndef PIC_PUSH_LDS_SLOTS
 #define PIC_PUSH_LDS_SLOTS 3072
 #endif
-#ifndef PIC_PUSH_UNROLL
-#define PIC_PUSH_UNROLL 2
+#ifndef PIC_PUSH_DEPTH
+#define PIC_PUSH_DEPTH 2
 #endif
-#ifndef PIC_PUSH_PREFETCH
-#define PIC_PUSH_PREFETCH 1
-#endif
+
 #ifndef PIC_PUSH_MIN_WAVES
 #define PIC_PUSH_MIN_WAVES 0
 #endif
@@ -53,7 +51,7 @@ constexpr int kBatchPPT = PIC_BATCH_PPT;
 constexpr int kBatchTile = kThreads * kBatchPPT;
 constexpr int kMinTile = kTile < kBatchTile ? kTile : kBatchTile;
 constexpr int kLdsSlots = PIC_PUSH_LDS_SLOTS;  // 64-bit LDS current accumulators per work-group
-constexpr int kUnroll = PIC_PUSH_UNROLL;      // push loop unroll
+constexpr int kDepth = PIC_PUSH_DEPTH;        // particles per thread whose loads are in flight
 constexpr int kLanes = 64;            // wavefront width
 constexpr int kFieldChunk = 256;      // nodes per field work-group
 constexpr int kTwo24 = 1 << 24;
@@ -157,6 +155,68 @@ __device__ __forceinline__ int wave_max(int v) {
   return v;
 }
 
+// Row-local reductions with DPP lane shifts (rows of 16 lanes).  After the
+// steps 1, 2, .., N/2 of an inclusive shift-and-combine scan, the last lane of
+// every aligned group of N lanes holds the group's result.  All lanes of the
+// wave must be active.  Lanes shifted in from outside the row read `old`.
+template <int N>
+__device__ __forceinline__ int row_shr(int old, int v) {
+  return __builtin_amdgcn_update_dpp(old, v, 0x110 + N, 0xf, 0xf, false);
+}
+template <int N>
+__device__ __forceinline__ unsigned long long row_shr64(unsigned long long v) {
+  const unsigned lo = (unsigned)row_shr<N>(0, (int)(unsigned)v);
+  const unsigned hi = (unsigned)row_shr<N>(0, (int)(unsigned)(v >> 32));
+  return ((unsigned long long)hi << 32) | lo;
+}
+// sum over aligned groups of g lanes, g in {1, 2, 4, 8, 16} (wave-uniform)
+__device__ __forceinline__ long long group_sum(long long v, int g) {
+  if (g >= 2) v += (long long)row_shr64<1>((unsigned long long)v);
+  if (g >= 4) v += (long long)row_shr64<2>((unsigned long long)v);
+  if (g >= 8) v += (long long)row_shr64<4>((unsigned long long)v);
+  if (g >= 16) v += (long long)row_shr64<8>((unsigned long long)v);
+  return v;
+}
+// wave sum in a fixed order: rows by DPP, then the four row sums
+__device__ __forceinline__ double wave_sum_dpp(double x) {
+  unsigned long long b = __double_as_longlong(x);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    unsigned long long t = 0;
+    switch (k) {
+      case 0: t = row_shr64<1>(b); break;
+      case 1: t = row_shr64<2>(b); break;
+      case 2: t = row_shr64<4>(b); break;
+      default: t = row_shr64<8>(b); break;
+    }
+    b = __double_as_longlong(__longlong_as_double(b) + __longlong_as_double(t));
+  }
+  const unsigned lo = (unsigned)b, hi = (unsigned)(b >> 32);
+  double r[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    r[k] = __longlong_as_double(((long long)__builtin_amdgcn_readlane((int)hi, 16 * k + 15) << 32) |
+                                (unsigned)__builtin_amdgcn_readlane((int)lo, 16 * k + 15));
+  return (r[0] + r[1]) + (r[2] + r[3]);
+}
+// wave minimum and maximum, wave-uniform results
+__device__ __forceinline__ int wave_min_dpp(int v) {
+  v = min(v, row_shr<1>(v, v));
+  v = min(v, row_shr<2>(v, v));
+  v = min(v, row_shr<4>(v, v));
+  v = min(v, row_shr<8>(v, v));
+  return min(min(__builtin_amdgcn_readlane(v, 15), __builtin_amdgcn_readlane(v, 31)),
+             min(__builtin_amdgcn_readlane(v, 47), __builtin_amdgcn_readlane(v, 63)));
+}
+__device__ __forceinline__ int wave_max_dpp(int v) {
+  v = max(v, row_shr<1>(v, v));
+  v = max(v, row_shr<2>(v, v));
+  v = max(v, row_shr<4>(v, v));
+  v = max(v, row_shr<8>(v, v));
+  return max(max(__builtin_amdgcn_readlane(v, 15), __builtin_amdgcn_readlane(v, 31)),
+             max(__builtin_amdgcn_readlane(v, 47), __builtin_amdgcn_readlane(v, 63)));
+}
+
 // Position update of the deposition contract: gamma from the stored
 // momentum in the order ((1 + ux^2) + uy^2) + uz^2, correctly rounded square
 // root and division, displacement vx*cfl, offset renormalised to [0, 1).
@@ -190,15 +250,18 @@ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
 
 // Current accumulation of one push work-group: an LDS window of W storage
 // indices (starting at wlo) covering every node the tile's particles can
-// touch, with R = 2^rshift private copies per slot (lane & (R - 1) picks
-// the copy), so lanes of a wave that hit the same node add to different
-// words.  Tiles whose window does not fit use global atomics instead.
+// touch, with R = 2^k private copies per slot (lane & (R - 1) picks the
+// copy), so lanes of a wave that hit the same node add to different words.
+// Tiles whose window does not fit use global atomics instead.
 struct DepositCtx {
-  unsigned long long* lds;  // [3][W][R], current / qw_ref of particles with qw == qw_ref
+  // current / qw_ref of particles with qw == qw_ref: slot (comp, cell) of
+  // copy k at lds[(comp * W + cell) * P + k], P = R + 1 (R > 1) or 1; the
+  // odd stride spreads one copy of neighbouring slots over distinct banks
+  unsigned long long* lds;
   unsigned long long* J[3];
   int wlo;
   int W;
-  int rshift;
+  int P;
   int copy;
   int qw_ref;
   bool use_lds;
@@ -236,8 +299,8 @@ __device__ __forceinline__ void deposit(DepositCtx& d, int c, R o, int c1, R o1,
     // LDS holds sums of unweighted terms; the flush multiplies by qw_ref
     const int r = j0 - d.wlo;  // 0 <= r <= W - 3 by construction of the window
     // slot (comp, r + k) of this lane's copy: x0 + comp * cs + k * ss
-    const int ss = 1 << d.rshift, cs = d.W << d.rshift;
-    unsigned long long* x0 = d.lds + d.copy + (r << d.rshift);
+    const int ss = d.P, cs = d.W * d.P;
+    unsigned long long* x0 = d.lds + d.copy + r * d.P;
     unsigned long long* y0 = x0 + cs;
     unsigned long long* z0 = y0 + cs;
     atomicAdd(x0, (unsigned long long)(long long)F0);
@@ -274,15 +337,20 @@ struct PushAcc {
 // Stored state of one particle (besides its cell).
 template <typename R>
 struct PData {
+  int c;
   R o, ux, uy, uz, w;
   float rx, ry, rz;
 };
 
+// All loads of one particle are independent of each other, so a thread keeps
+// several particles' loads in flight while it computes an earlier one.
 template <typename R, bool COMP>
-__device__ __forceinline__ PData<R> load_particle(const SpeciesDev<R>& sp, int i, int c) {
+__device__ __forceinline__ PData<R> load_particle(const SpeciesDev<R>& sp, int i, int n) {
   PData<R> d{};
-  if (c != kDead) {
+  d.c = kDead;
+  if (i < n) {
     const unsigned ui = (unsigned)i;
+    d.c = ld(sp.cell, ui);
     d.o = ld(sp.off, ui);
     d.ux = ld(sp.ux, ui);
     d.uy = ld(sp.uy, ui);
@@ -300,8 +368,9 @@ __device__ __forceinline__ PData<R> load_particle(const SpeciesDev<R>& sp, int i
 // One particle: gather, Boris, RR, move, deposit, store.
 template <typename R, bool RR, bool COMP>
 __device__ __forceinline__ void push_particle(const PushArgs<R>& a, const SpeciesDev<R>& sp,
-                                              int s, int i, int c, const PData<R>& pd,
+                                              int s, int i, const PData<R>& pd,
                                               DepositCtx& dc, PushAcc& acc) {
+  const int c = pd.c;
   if (c == kDead) return;
   const unsigned ui = (unsigned)i;
   const R o = pd.o, ux = pd.ux, uy = pd.uy, uz = pd.uz, w = pd.w;
@@ -419,29 +488,30 @@ __device__ __forceinline__ void push_particle(const PushArgs<R>& a, const Specie
 template <typename R, bool RR, bool COMP, int PPT>
 __device__ __forceinline__ void push_tile(const PushArgs<R>& a, int s, int tile, int n, int base,
                                           unsigned long long* lds) {
+  static_assert(PPT % kDepth == 0, "the load ring must divide the tile");
   __shared__ int s_mn[kThreads / kLanes], s_mx[kThreads / kLanes];
   __shared__ double s_red[3][kThreads / kLanes];
   const SpeciesDev<R> sp = a.sp[s];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
 
-  // cells of this thread's particles and the tile's cell range
-  int cl[PPT];
+  // the first particles' loads overlap the window set-up below
+  PData<R> ring[kDepth];
+#pragma unroll
+  for (int k = 0; k < kDepth; ++k) ring[k] = load_particle<R, COMP>(sp, base + k * kThreads + tid, n);
+
+  // the tile's cell range
   int cmin = INT_MAX, cmax = INT_MIN;
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
     const int i = base + k * kThreads + tid;
-    cl[k] = i < n ? ld(sp.cell, (unsigned)i) : kDead;
-    if (cl[k] != kDead) {
-      cmin = min(cmin, cl[k]);
-      cmax = max(cmax, cl[k]);
+    const int c = i < n ? ld(sp.cell, (unsigned)i) : kDead;
+    if (c != kDead) {
+      cmin = min(cmin, c);
+      cmax = max(cmax, c);
     }
   }
-#if PIC_PUSH_PREFETCH
-  // first particle's loads overlap the window set-up below
-  PData<R> cur = load_particle<R, COMP>(sp, base + tid, cl[0]);
-#endif
-  cmin = wave_min(cmin);
-  cmax = wave_max(cmax);
+  cmin = wave_min_dpp(cmin);
+  cmax = wave_max_dpp(cmax);
   if (lane == 0) {
     s_mn[wid] = cmin;
     s_mx[wid] = cmax;
@@ -451,7 +521,8 @@ __device__ __forceinline__ void push_tile(const PushArgs<R>& a, int s, int tile,
   cmax = max(max(s_mx[0], s_mx[1]), max(s_mx[2], s_mx[3]));
   if (cmin > cmax) return;  // every particle of the tile was removed
 
-  // window: storage indices cmin .. cmax + 3 (nodes cmin - 1 .. cmax + 2)
+  // window: storage indices cmin .. cmax + 3 (nodes cmin - 1 .. cmax + 2),
+  // with as many private copies per slot (up to 64) as the LDS holds
   DepositCtx dc;
   dc.lds = lds;
   dc.J[0] = a.J[0];
@@ -461,37 +532,30 @@ __device__ __forceinline__ void push_tile(const PushArgs<R>& a, int s, int tile,
   dc.W = cmax - cmin + 4;
   dc.qw_ref = a.qw_ref[s];
   int sh = 6;
-  while (sh > 0 && 3 * dc.W * (1 << sh) > kLdsSlots) --sh;
-  dc.rshift = sh;
+  while (sh > 0 && 3 * dc.W * ((1 << sh) + 1) > kLdsSlots) --sh;
+  dc.P = sh ? (1 << sh) + 1 : 1;
   dc.copy = lane & ((1 << sh) - 1);
-  const int E = 3 * dc.W * (1 << sh);
+  const int E = 3 * dc.W * dc.P;
   dc.use_lds = E <= kLdsSlots;
   if (dc.use_lds)
     for (int e = tid; e < E; e += kThreads) lds[e] = 0ull;
   __syncthreads();
 
   PushAcc acc{0.f, 0.f, 0.f};
-#if PIC_PUSH_PREFETCH
-  // the next particle's loads are in flight while this one is computed
-#pragma unroll kUnroll
-  for (int k = 0; k < PPT; ++k) {
-    const int i = base + k * kThreads + tid;
-    PData<R> nxt{};
-    if (k + 1 < PPT) nxt = load_particle<R, COMP>(sp, i + kThreads, cl[k + 1]);
-    push_particle<R, RR, COMP>(a, sp, s, i, cl[k], cur, dc, acc);
-    cur = nxt;
+  // ring slot j holds particle k0 + j; its successor kDepth ahead is loaded
+  // before particle k0 + j is computed
+  for (int k0 = 0; k0 < PPT; k0 += kDepth) {
+#pragma unroll
+    for (int j = 0; j < kDepth; ++j) {
+      const int i = base + (k0 + j) * kThreads + tid;
+      const PData<R> cur = ring[j];
+      if (k0 + j + kDepth < PPT) ring[j] = load_particle<R, COMP>(sp, i + kDepth * kThreads, n);
+      push_particle<R, RR, COMP>(a, sp, s, i, cur, dc, acc);
+    }
   }
-#else
-#pragma unroll kUnroll
-  for (int k = 0; k < PPT; ++k) {
-    const int i = base + k * kThreads + tid;
-    const PData<R> pd = load_particle<R, COMP>(sp, i, cl[k]);
-    push_particle<R, RR, COMP>(a, sp, s, i, cl[k], pd, dc, acc);
-  }
-#endif
 
-  const double r0 = wave_sum((double)acc.rad), r1 = wave_sum((double)acc.esc),
-               r2 = wave_sum((double)acc.stiff);
+  const double r0 = wave_sum_dpp((double)acc.rad), r1 = wave_sum_dpp((double)acc.esc),
+               r2 = wave_sum_dpp((double)acc.stiff);
   if (lane == 0) {
     s_red[0][wid] = r0;
     s_red[1][wid] = r1;
@@ -499,17 +563,22 @@ __device__ __forceinline__ void push_tile(const PushArgs<R>& a, int s, int tile,
   }
   __syncthreads();
 
-  // one global atomic per window slot and component: each group of R lanes
-  // holds the R copies of one slot
+  // flush: g lanes per slot each sum R / g copies, DPP adds the g partial
+  // sums, and the group's last lane issues one global atomic
   if (dc.use_lds) {
-    const int Rm = (1 << sh) - 1;
-    for (int e0 = wid * kLanes; e0 < E; e0 += kThreads) {
-      const int e = e0 + lane;
-      long long v = e < E ? (long long)lds[e] : 0ll;
-      for (int o = 1; o <= Rm; o <<= 1) v += __shfl_xor(v, o);
-      if ((lane & Rm) == 0 && e < E && v != 0) {
-        const int slot = e >> sh;
-        const int comp = slot / dc.W, j = slot - comp * dc.W;
+    const int nc = 1 << sh;  // copies per slot
+    const int gsh = sh < 4 ? sh : 4, g = 1 << gsh;
+    const int S = 3 * dc.W, gi = tid >> gsh, t = tid & (g - 1);
+    for (int s0 = 0; s0 < S; s0 += kThreads >> gsh) {
+      const int sl = s0 + gi;
+      long long v = 0;
+      if (sl < S) {
+        const unsigned long long* q = lds + sl * dc.P + t;
+        for (int k = 0; k < nc; k += g) v += (long long)q[k];
+      }
+      v = group_sum(v, g);
+      if (t == g - 1 && sl < S && v != 0) {
+        const int comp = sl / dc.W, j = sl - comp * dc.W;
         atomicAdd(a.J[comp] + dc.wlo + j, (unsigned long long)(v * (long long)dc.qw_ref));
       }
     }
@@ -607,6 +676,23 @@ __device__ __forceinline__ void field_chunk(const FieldArgs<R>& p, int chunk) {
   const int n = p.nx;
   const R a = p.a, ha = R(0.5) * p.a, dt = p.dt;
 
+  // loads needed only at the end are issued first, so that their latency
+  // overlaps the staged update below
+  const int h = i0 + t;  // this thread's half-node (and node) output
+  long long ex_old = 0, jx = 0;
+  if (h <= n + 1) {
+    ex_old = p.Ex_int[h];
+    jx = p.J[0][h];
+  }
+  // incident wave at t_{n+1/2} (work-group 0 only)
+  double ey_in = 0.0, ez_in = 0.0;
+  if (t == 0 && i0 == 0) {
+    const double th = ((double)*p.step + 0.5) * p.dtd;
+    const double f = envelope(th, p.tr, p.tf, p.tl);
+    ey_in = p.ay * f * sin(th);
+    ez_in = p.az * f * cos(th);
+  }
+
   for (int k = t; k < CH + 3; k += CH) {
     const int i = i0 - 2 + k;
     const bool ok = i >= 0 && i <= n;
@@ -640,12 +726,7 @@ __device__ __forceinline__ void field_chunk(const FieldArgs<R>& p, int chunk) {
   __syncthreads();
 
   // boundary guards at t_{n+1/2} (first-order Silver-Mueller with injection)
-  double ey_in = 0.0, ez_in = 0.0;
   if (t == 0 && i0 == 0) {
-    const double th = ((double)*p.step + 0.5) * p.dtd;
-    const double f = envelope(th, p.tr, p.tf, p.tl);
-    ey_in = p.ay * f * sin(th);
-    ez_in = p.az * f * cos(th);
     // h = 0 is LDS index 1; node 0 is sEy index 2, Jy node 0 is sJy index 1
     const R d = R(1) + a;
     sBz[1] = (R(4) * (R)ey_in - R(2) * sEy[2] - (R(1) - a) * sBz[2] + dt * sJy[1]) / d;
@@ -700,7 +781,6 @@ __device__ __forceinline__ void field_chunk(const FieldArgs<R>& p, int chunk) {
   if (i <= n) {
     p.out.N[i] = NodeF<R>{nEy[t + 1], nEz[t + 1]};
   }
-  const int h = i0 + t;
   if (h <= n + 1) {
     R bz, byv;
     if (h >= 1 && h <= n) {  // B^{n+1/2} -> B^{n+1}
@@ -710,7 +790,7 @@ __device__ __forceinline__ void field_chunk(const FieldArgs<R>& p, int chunk) {
       bz = sBz[t + 1];
       byv = sBy[t + 1];
     }
-    const long long ex = p.Ex_int[h] - p.J[0][h];
+    const long long ex = ex_old - jx;
     p.Ex_int[h] = ex;
     p.out.H[h] = HalfF<R>{(R)((double)ex * p.sEx), byv, bz, R(0)};
     p.Jnext[0][h] = 0ull;
@@ -824,32 +904,69 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(SortArgs<R> p) {
   sort_hist_block<R>(p, (int)blockIdx.x);
 }
 
-// exclusive scan of the per-cell counts of one species (one work-group);
-// the alive count goes to *new_count (the count slot of the destination
-// arrays) and the counts are cleared for the next histogram
+// inclusive prefix sum over the 64 lanes of a wave (all lanes active)
+__device__ __forceinline__ int wave_incl_scan(int v) {
+  v += row_shr<1>(0, v);
+  v += row_shr<2>(0, v);
+  v += row_shr<4>(0, v);
+  v += row_shr<8>(0, v);
+  const int r0 = __builtin_amdgcn_readlane(v, 15), r1 = __builtin_amdgcn_readlane(v, 31),
+            r2 = __builtin_amdgcn_readlane(v, 47);
+  const int row = (threadIdx.x & 63) >> 4;
+  return v + (row >= 1 ? r0 : 0) + (row >= 2 ? r1 : 0) + (row >= 3 ? r2 : 0);
+}
+
+// exclusive scan of the per-cell counts of one species (one work-group of
+// 1024 threads); the alive count goes to *new_count (the count slot of the
+// destination arrays) and the counts are cleared for the next histogram.
+// Chunks of 8192 cells pass through LDS so that every global access is
+// coalesced; within a chunk thread t scans cells 8t .. 8t + 7.
+constexpr int kScanThreads = 1024, kScanPer = 8, kScanChunk = kScanThreads * kScanPer;
 __device__ __forceinline__ void sort_scan_species(int* cnt, int* cur, long long* new_count, int nx) {
-  __shared__ int part[1024];
-  const int t = threadIdx.x;
-  const int per = (nx + 1023) / 1024;
-  const int lo = min(nx, t * per), hi = min(nx, lo + per);
-  int sum = 0;
-  for (int j = lo; j < hi; ++j) sum += cnt[j];
-  part[t] = sum;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const int v = t >= o ? part[t - o] : 0;
+  __shared__ int stage[kScanChunk];
+  __shared__ int wsum[kScanThreads / kLanes];
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  long long carry = 0;
+  for (int c0 = 0; c0 < nx; c0 += kScanChunk) {
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      const int j = c0 + k * kScanThreads + t;
+      stage[k * kScanThreads + t] = j < nx ? cnt[j] : 0;
+    }
     __syncthreads();
-    part[t] += v;
+    int v[kScanPer], sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      v[k] = stage[t * kScanPer + k];
+      sum += v[k];
+    }
+    const int incl = wave_incl_scan(sum);
+    if (lane == 63) wsum[wid] = incl;
     __syncthreads();
+    int before = 0, total = 0;
+    for (int w = 0; w < kScanThreads / kLanes; ++w) {
+      before += w < wid ? wsum[w] : 0;
+      total += wsum[w];
+    }
+    int run = (int)carry + before + incl - sum;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      stage[t * kScanPer + k] = run;
+      run += v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      const int j = c0 + k * kScanThreads + t;
+      if (j < nx) {
+        cur[j] = stage[k * kScanThreads + t];
+        cnt[j] = 0;
+      }
+    }
+    carry += total;
+    __syncthreads();  // stage and wsum are reused by the next chunk
   }
-  int run = part[t] - sum;
-  for (int j = lo; j < hi; ++j) {
-    const int c = cnt[j];
-    cur[j] = run;
-    run += c;
-    cnt[j] = 0;
-  }
-  if (t == 1023) *new_count = part[1023];
+  if (t == 0) *new_count = carry;
 }
 
 __global__ __launch_bounds__(1024) void k_sort_scan(int* cnt0, int* cnt1, int* cur0, int* cur1,
@@ -988,8 +1105,10 @@ __device__ __forceinline__ SlotRanges load_ranges(const int* start, int n, int* 
 template <typename R>
 __global__ PIC_PUSH_BOUNDS void k_push_batch(const SlotDev<R>* __restrict__ slots, const int* __restrict__ start, int n) {
   __shared__ unsigned long long lds[kLdsSlots];
-  __shared__ int rng[kMaxSlots + 1];
-  const SlotRanges sr = load_ranges(start, n, rng);
+  // the slot ranges are read before the tile's first barrier and the deposit
+  // window is cleared only after it, so the two share the LDS
+  static_assert((kMaxSlots + 1) * sizeof(int) <= sizeof(lds), "slot ranges must fit the window");
+  const SlotRanges sr = load_ranges(start, n, reinterpret_cast<int*>(lds));
   const int b = (int)blockIdx.x;
   if (b >= sr.total()) return;
   const int sl = sr.slot(b);
