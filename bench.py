@@ -23,6 +23,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+# per-kernel durations come from HIP events around every TIMING_PERIOD-th
+# launch of each kernel kind (events around every launch add queue time)
+TIMING_PERIOD = 8
 
 
 def kernel_hash() -> str:
@@ -45,7 +48,7 @@ def alg_bytes_per_push(precision: str, compensated: bool, rr: bool):
     return ele, ion
 
 
-def time_run(cfg, steps, warmup, diag_every, timing=True):
+def time_run(cfg, steps, warmup, diag_every, timing=TIMING_PERIOD):
     import torch
 
     from paper_1008_1685_amd import Run
@@ -66,7 +69,7 @@ def time_run(cfg, steps, warmup, diag_every, timing=True):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kt = run.timing_read()
-    run.timing(False)
+    run.timing(0)
     d1 = run.diag()
     n_e = 0.5 * (d0["n_alive"][0] + d1["n_alive"][0])
     n_i = 0.5 * (d0["n_alive"][1] + d1["n_alive"][1])
@@ -222,14 +225,17 @@ def main():
                       frac=achieved / PEAK_HBM_GBS, traffic=traffic,
                       kernel="k_push", bytes_per_launch=bytes_per_launch,
                       avg_launch_us=avg_push_s * 1e6, alg_bytes_per_push=dict(electron=be, ion=bi)),
-        kernel_ms_per_step={k: v[0] / max(args.steps, 1) for k, v in res["kernels"].items()},
+        kernel_us_per_launch={k: v[0] * 1e3 / max(v[1], 1) for k, v in res["kernels"].items()},
+        kernel_ms_per_step={k: v[0] / max(v[1], 1) * (1.0 / cfg["sort_interval"] if k == "sort" else 1.0)
+                            for k, v in res["kernels"].items()},
+        timing=f"HIP events around every {TIMING_PERIOD}th launch of each kernel",
         energy_balance=res["diag1"]["balance"] / max(res["diag1"]["E_in"], 1e-300),
         gauss_int=res["diag1"]["gauss_int"],
     )
     if not args.no_side_runs:
         side = max(args.steps // 4, 200)
-        r_off = time_run(dict(cfg, rr=False), side, args.warmup, args.diag_every, timing=True)
-        r_64 = time_run(dict(cfg, precision="fp64"), side, args.warmup, args.diag_every, timing=True)
+        r_off = time_run(dict(cfg, rr=False), side, args.warmup, args.diag_every)
+        r_64 = time_run(dict(cfg, precision="fp64"), side, args.warmup, args.diag_every)
         v_off = (r_off["n_e"] + r_off["n_i"]) * side / r_off["seconds"]
         v_64 = (r_64["n_e"] + r_64["n_i"]) * side / r_64["seconds"]
         line["rr_cost"] = dict(pushes_per_s_rr_off=v_off, overhead=v_off / value - 1.0,

@@ -217,11 +217,14 @@ pic_status pic_set_state(struct pic_run* run, const pic_state* st, void* stream)
 pic_status pic_spectrum(struct pic_run* run, int32_t bins, double e_max_mev,
                         double* host_hist, void* stream);
 
-/* Per-kernel timing for profiling: when enabled, pic_step records HIP
- * events around each kernel it launches.  pic_timing_read synchronises the
- * stream and returns accumulated milliseconds and launch counts for
- * kernel k = 0 push-deposit, 1 field advance, 2 sort (all passes). */
-pic_status pic_timing_enable(struct pic_run* run, int32_t enable);
+/* Per-kernel timing for profiling: with period p > 0, pic_step records HIP
+ * events around every p-th launch of each kernel kind (p = 1: every launch;
+ * an event pair costs several microseconds of queue time, so sampling keeps
+ * the timed steps close to untimed ones); p = 0 turns timing off and
+ * p < 0 is PIC_EINVAL.  pic_timing_read synchronises the stream and returns
+ * the accumulated milliseconds and the number of timed launches for kernel
+ * k = 0 push-deposit, 1 field advance, 2 sort (all passes). */
+pic_status pic_timing_enable(struct pic_run* run, int32_t period);
 pic_status pic_timing_read(struct pic_run* run, double ms[3], int64_t launches[3],
                            void* stream);
 

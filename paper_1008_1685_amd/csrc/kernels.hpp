@@ -819,7 +819,7 @@ struct SortArgs {
 };
 
 constexpr int kSortThreads = 256;
-constexpr int kSortPPT = 16;                       // particles per thread per sort tile
+constexpr int kSortPPT = 8;                        // particles per thread per sort tile
 constexpr int kSortTile = kSortThreads * kSortPPT;
 constexpr int kSortWin = 4096;                     // LDS cell window of a sort tile
 
@@ -851,8 +851,8 @@ __device__ __forceinline__ void tile_range(const int* cl, int& lo, int& hi, int*
       a = min(a, cl[k]);
       b = max(b, cl[k]);
     }
-  a = wave_min(a);
-  b = wave_max(b);
+  a = wave_min_dpp(a);
+  b = wave_max_dpp(b);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   __syncthreads();  // earlier readers of sm (previous tile) are done
   if (lane == 0) {
@@ -992,10 +992,28 @@ __device__ __forceinline__ void sort_scatter_block(const SortArgs<R>& p, int blk
   const SpeciesDev<R> src = p.src[s], dst = p.dst[s];
   const bool comp = s == 0 && p.comp;
   int cl[kSortPPT], pos[kSortPPT];
+  // the particles' data is loaded with their cells, so that its latency
+  // overlaps the position claims below
+  R off[kSortPPT], ux[kSortPPT], uy[kSortPPT], uz[kSortPPT], w[kSortPPT];
+  float rx[kSortPPT], ry[kSortPPT], rz[kSortPPT];
 #pragma unroll
   for (int k = 0; k < kSortPPT; ++k) {
     const long long i = base + k * kSortThreads + threadIdx.x;
-    cl[k] = i < n ? src.cell[i] : kDead;
+    cl[k] = kDead;
+    if (i < n) {
+      const unsigned ui = (unsigned)i;
+      cl[k] = ld(src.cell, ui);
+      off[k] = ld(src.off, ui);
+      ux[k] = ld(src.ux, ui);
+      uy[k] = ld(src.uy, ui);
+      uz[k] = ld(src.uz, ui);
+      w[k] = ld(src.w, ui);
+      if (comp) {
+        rx[k] = ld(src.rx, ui);
+        ry[k] = ld(src.ry, ui);
+        rz[k] = ld(src.rz, ui);
+      }
+    }
   }
   int lo, hi;
   tile_range(cl, lo, hi, sm);
@@ -1017,21 +1035,20 @@ __device__ __forceinline__ void sort_scatter_block(const SortArgs<R>& p, int blk
 #pragma unroll
     for (int k = 0; k < kSortPPT; ++k) pos[k] = wave_claim(p.cursor[s], cl[k], cl[k] != kDead);
   }
-#pragma unroll 4
+#pragma unroll
   for (int k = 0; k < kSortPPT; ++k) {
     if (cl[k] == kDead) continue;
-    const long long i = base + k * kSortThreads + threadIdx.x;
-    const int j = pos[k];
-    dst.cell[j] = cl[k];
-    dst.off[j] = src.off[i];
-    dst.ux[j] = src.ux[i];
-    dst.uy[j] = src.uy[i];
-    dst.uz[j] = src.uz[i];
-    dst.w[j] = src.w[i];
+    const unsigned j = (unsigned)pos[k];
+    st(dst.cell, j, cl[k]);
+    st(dst.off, j, off[k]);
+    st(dst.ux, j, ux[k]);
+    st(dst.uy, j, uy[k]);
+    st(dst.uz, j, uz[k]);
+    st(dst.w, j, w[k]);
     if (comp) {
-      dst.rx[j] = src.rx[i];
-      dst.ry[j] = src.ry[i];
-      dst.rz[j] = src.rz[i];
+      st(dst.rx, j, rx[k]);
+      st(dst.ry, j, ry[k]);
+      st(dst.rz, j, rz[k]);
     }
   }
 }

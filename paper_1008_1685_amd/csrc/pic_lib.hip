@@ -143,8 +143,9 @@ struct pic_run {
   unsigned long long* hist;
   int tiles_max;
   struct pic_batch* batch = nullptr;  // set while the run is stepped by a batch
-  // timing
-  bool timing = false;
+  // timing: every timing-th launch of each kernel kind is bracketed by events
+  int timing = 0;
+  long long seen[3] = {0, 0, 0};
   std::vector<TimingRec> ev;
   size_t ev_next = 0;
   double ms[3] = {0, 0, 0};
@@ -216,8 +217,12 @@ __global__ void k_set_counts(long long* dst, long long a, long long b) {
 
 hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+constexpr size_t kNoEvent = ~(size_t)0;
+
 pic_status ev_begin(pic_run* r, int kind, hipStream_t st, size_t* slot) {
+  *slot = kNoEvent;
   if (!r->timing) return PIC_OK;
+  if (r->seen[kind]++ % r->timing) return PIC_OK;  // not sampled
   if (r->ev.empty()) {
     r->ev.resize(512);
     for (auto& e : r->ev) {
@@ -242,7 +247,7 @@ pic_status ev_begin(pic_run* r, int kind, hipStream_t st, size_t* slot) {
 }
 
 pic_status ev_end(pic_run* r, hipStream_t st, size_t slot) {
-  if (!r->timing) return PIC_OK;
+  if (slot == kNoEvent) return PIC_OK;
   TimingRec& e = r->ev[slot];
   HIP_TRY(hipEventRecord(e.b, st));
   e.used = true;
@@ -917,9 +922,11 @@ pic_status pic_spectrum(pic_run* r, int32_t bins, double e_max, double* host_his
   return PIC_OK;
 }
 
-pic_status pic_timing_enable(pic_run* r, int32_t enable) {
+pic_status pic_timing_enable(pic_run* r, int32_t period) {
   if (!r) return fail(PIC_EINVAL, "null run");
-  r->timing = enable != 0;
+  if (period < 0) return fail(PIC_EINVAL, "negative timing period");
+  r->timing = period;
+  for (auto& k : r->seen) k = 0;
   return PIC_OK;
 }
 

@@ -198,8 +198,10 @@ class Run:
         return h
 
     # ------------------------------------------------------------ timing
-    def timing(self, enable: bool):
-        N.check(self.lib.pic_timing_enable(self._h, 1 if enable else 0), "pic_timing_enable")
+    def timing(self, period):
+        """Time every ``period``-th launch of each kernel kind (True: every
+        launch, False or 0: off)."""
+        N.check(self.lib.pic_timing_enable(self._h, int(period)), "pic_timing_enable")
 
     def timing_read(self):
         ms = (C.c_double * 3)()
