@@ -129,7 +129,7 @@ def serve_bench(n_runs=256, rate=20.0, seed=0, max_slots=64, budget_gb=64.0):
 
 def write_traffic(fetch, write, cfetch, cwrite, out_path):
     """profiles/traffic.json from rocprofv3 counter_collection.csv files:
-    FETCH_SIZE and WRITE_SIZE of this benchmark (--steps 50 --warmup 3550
+    FETCH_SIZE and WRITE_SIZE of this benchmark (--steps 50 --warmup 3950
     --no-side-runs --no-serve) and of a plain 1 GiB device copy
     (torch b.copy_(a), the calibration of bytes reported per byte moved)."""
     import csv

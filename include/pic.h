@@ -217,6 +217,17 @@ pic_status pic_set_state(struct pic_run* run, const pic_state* st, void* stream)
 pic_status pic_spectrum(struct pic_run* run, int32_t bins, double e_max_mev,
                         double* host_hist, void* stream);
 
+/* Self-check of the move arithmetic (the correctly rounded square root and
+ * reciprocal of the deposition contract are computed from hardware estimates
+ * plus FMA corrections): for every float whose bit pattern lies in
+ * [first, first + count) and that is finite and >= 1, compare with the
+ * compiler's correctly rounded sqrtf and 1.0f / x (the reciprocal below 2^126
+ * only) and add the number of differing results to *d_mismatches, a device
+ * counter the caller zeroes and reads.  Asynchronous on stream; first + count
+ * above 2^32 is PIC_EINVAL. */
+pic_status pic_check_rounding(uint32_t first, uint32_t count, unsigned long long* d_mismatches,
+                              void* stream);
+
 /* Per-kernel timing for profiling: with period p > 0, pic_step records HIP
  * events around every p-th launch of each kernel kind (p = 1: every launch;
  * an event pair costs several microseconds of queue time, so sampling keeps

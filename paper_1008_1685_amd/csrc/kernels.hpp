@@ -36,6 +36,9 @@ namespace pic {
 #ifndef PIC_PUSH_DEPTH
 #define PIC_PUSH_DEPTH 2
 #endif
+#ifndef PIC_RING_UNROLL
+#define PIC_RING_UNROLL 2
+#endif
 
 #ifndef PIC_PUSH_MIN_WAVES
 #define PIC_PUSH_MIN_WAVES 0
@@ -52,6 +55,7 @@ constexpr int kBatchTile = kThreads * kBatchPPT;
 constexpr int kMinTile = kTile < kBatchTile ? kTile : kBatchTile;
 constexpr int kLdsSlots = PIC_PUSH_LDS_SLOTS;  // 64-bit LDS current accumulators per work-group
 constexpr int kDepth = PIC_PUSH_DEPTH;        // particles per thread whose loads are in flight
+constexpr int kRingUnroll = PIC_RING_UNROLL;  // ring turns per loop iteration (renames, no copies)
 constexpr int kLanes = 64;            // wavefront width
 constexpr int kFieldChunk = 256;      // nodes per field work-group
 constexpr int kTwo24 = 1 << 24;
@@ -217,6 +221,27 @@ __device__ __forceinline__ int wave_max_dpp(int v) {
              max(__builtin_amdgcn_readlane(v, 47), __builtin_amdgcn_readlane(v, 63)));
 }
 
+// Correctly rounded square root and reciprocal for arguments >= 1, from the
+// hardware estimates (within one ulp) and exact FMA residuals: the root
+// picks among s - ulp, s, s + ulp by the signs of x - s' s; the reciprocal
+// takes one Newton step r + r (1 - x r).  Compared exhaustively with the
+// compiler's correctly rounded sqrtf and 1.0f / x (pic_check_rounding), they
+// agree on every float in [1, 2^128) and [1, 2^126) respectively; infinity
+// and NaN propagate.
+__device__ __forceinline__ float sqrt_rn_ge1(float x) {
+  const float s = __builtin_amdgcn_sqrtf(x);
+  const float sd = __int_as_float(__float_as_int(s) - 1), su = __int_as_float(__float_as_int(s) + 1);
+  const float rd = fmaf(-sd, s, x), ru = fmaf(-su, s, x);
+  const float r = rd <= 0.f ? sd : s;
+  return ru > 0.f ? su : r;
+}
+__device__ __forceinline__ float rcp_rn_ge1(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(fmaf(-x, r, 1.0f), r, r);
+}
+__device__ __forceinline__ double sqrt_rn_ge1(double x) { return sqrt(x); }
+__device__ __forceinline__ double rcp_rn_ge1(double x) { return 1.0 / x; }
+
 // Position update of the deposition contract: gamma from the stored
 // momentum in the order ((1 + ux^2) + uy^2) + uz^2, correctly rounded square
 // root and division, displacement vx*cfl, offset renormalised to [0, 1).
@@ -224,8 +249,8 @@ template <typename R>
 __device__ __forceinline__ void contract_move(R ux, R uy, R uz, R o, R cfl, R& g,
                                               R& vy, R& vz, R& o1, R& s) {
 #pragma clang fp contract(off)
-  g = sqrt(((R(1) + ux * ux) + uy * uy) + uz * uz);
-  const R ig = R(1) / g;
+  g = sqrt_rn_ge1(((R(1) + ux * ux) + uy * uy) + uz * uz);
+  const R ig = rcp_rn_ge1(g);
   const R vx = ux * ig;
   vy = uy * ig;
   vz = uz * ig;
@@ -314,16 +339,21 @@ __device__ __forceinline__ void deposit(DepositCtx& d, int c, R o, int c1, R o1,
       atomicAdd(z0 + 2 * ss, (unsigned long long)(long long)tz2);
     }
   } else {
+    // keep the 64-bit products of this rare path out of the common one
+    int F1m = F1, ty2m = ty2, tz2m = tz2;
+    int t[5] = {F0, ty0, ty1, tz0, tz1};
+    asm volatile("" : "+v"(t[0]), "+v"(t[1]), "+v"(t[2]), "+v"(t[3]), "+v"(t[4]), "+v"(F1m), "+v"(ty2m),
+                 "+v"(tz2m));
     const long long q = qw;
-    atomicAdd(d.J[0] + j0, (unsigned long long)(q * F0));
-    atomicAdd(d.J[1] + j0, (unsigned long long)(q * ty0));
-    atomicAdd(d.J[1] + j0 + 1, (unsigned long long)(q * ty1));
-    atomicAdd(d.J[2] + j0, (unsigned long long)(q * tz0));
-    atomicAdd(d.J[2] + j0 + 1, (unsigned long long)(q * tz1));
+    atomicAdd(d.J[0] + j0, (unsigned long long)(q * t[0]));
+    atomicAdd(d.J[1] + j0, (unsigned long long)(q * t[1]));
+    atomicAdd(d.J[1] + j0 + 1, (unsigned long long)(q * t[2]));
+    atomicAdd(d.J[2] + j0, (unsigned long long)(q * t[3]));
+    atomicAdd(d.J[2] + j0 + 1, (unsigned long long)(q * t[4]));
     if (moved) {
-      atomicAdd(d.J[0] + j0 + 1, (unsigned long long)(q * F1));
-      atomicAdd(d.J[1] + j0 + 2, (unsigned long long)(q * ty2));
-      atomicAdd(d.J[2] + j0 + 2, (unsigned long long)(q * tz2));
+      atomicAdd(d.J[0] + j0 + 1, (unsigned long long)(q * F1m));
+      atomicAdd(d.J[1] + j0 + 2, (unsigned long long)(q * ty2m));
+      atomicAdd(d.J[2] + j0 + 2, (unsigned long long)(q * tz2m));
     }
   }
 }
@@ -344,23 +374,27 @@ struct PData {
 
 // All loads of one particle are independent of each other, so a thread keeps
 // several particles' loads in flight while it computes an earlier one.
+// Past the end of the species (i >= n, last tile only) the loads read
+// particle n - 1 instead, so that they need no branch, and the particle is
+// marked removed.  n >= 1.
 template <typename R, bool COMP>
 __device__ __forceinline__ PData<R> load_particle(const SpeciesDev<R>& sp, int i, int n) {
-  PData<R> d{};
-  d.c = kDead;
-  if (i < n) {
-    const unsigned ui = (unsigned)i;
-    d.c = ld(sp.cell, ui);
-    d.o = ld(sp.off, ui);
-    d.ux = ld(sp.ux, ui);
-    d.uy = ld(sp.uy, ui);
-    d.uz = ld(sp.uz, ui);
-    d.w = ld(sp.w, ui);
-    if (COMP) {
-      d.rx = ld(sp.rx, ui);
-      d.ry = ld(sp.ry, ui);
-      d.rz = ld(sp.rz, ui);
-    }
+  PData<R> d;
+  const bool in = i < n;
+  const unsigned ui = (unsigned)(in ? i : n - 1);
+  d.c = ld(sp.cell, ui);
+  if (!in) d.c = kDead;
+  d.o = ld(sp.off, ui);
+  d.ux = ld(sp.ux, ui);
+  d.uy = ld(sp.uy, ui);
+  d.uz = ld(sp.uz, ui);
+  d.w = ld(sp.w, ui);
+  if (COMP) {
+    d.rx = ld(sp.rx, ui);
+    d.ry = ld(sp.ry, ui);
+    d.rz = ld(sp.rz, ui);
+  } else {
+    d.rx = d.ry = d.rz = 0.f;
   }
   return d;
 }
@@ -485,26 +519,33 @@ __device__ __forceinline__ void push_particle(const PushArgs<R>& a, const Specie
   }
 }
 
-template <typename R, bool RR, bool COMP, int PPT>
+// PPT particles per thread, D of them with loads in flight (D = PPT: the
+// whole tile is loaded up front)
+template <typename R, bool RR, bool COMP, int PPT, int D>
 __device__ __forceinline__ void push_tile(const PushArgs<R>& a, int s, int tile, int n, int base,
                                           unsigned long long* lds) {
-  static_assert(PPT % kDepth == 0, "the load ring must divide the tile");
+  static_assert(PPT % D == 0, "the load ring must divide the tile");
   __shared__ int s_mn[kThreads / kLanes], s_mx[kThreads / kLanes];
   __shared__ double s_red[3][kThreads / kLanes];
   const SpeciesDev<R> sp = a.sp[s];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
 
   // the first particles' loads overlap the window set-up below
-  PData<R> ring[kDepth];
+  PData<R> ring[D];
 #pragma unroll
-  for (int k = 0; k < kDepth; ++k) ring[k] = load_particle<R, COMP>(sp, base + k * kThreads + tid, n);
+  for (int k = 0; k < D; ++k) ring[k] = load_particle<R, COMP>(sp, base + k * kThreads + tid, n);
 
-  // the tile's cell range
+  // the tile's cell range (from the ring when it holds the whole tile)
   int cmin = INT_MAX, cmax = INT_MIN;
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
-    const int i = base + k * kThreads + tid;
-    const int c = i < n ? ld(sp.cell, (unsigned)i) : kDead;
+    int c;
+    if constexpr (PPT == D) {
+      c = ring[k].c;
+    } else {
+      const int i = base + k * kThreads + tid;
+      c = i < n ? ld(sp.cell, (unsigned)i) : kDead;
+    }
     if (c != kDead) {
       cmin = min(cmin, c);
       cmax = max(cmax, c);
@@ -542,14 +583,15 @@ __device__ __forceinline__ void push_tile(const PushArgs<R>& a, int s, int tile,
   __syncthreads();
 
   PushAcc acc{0.f, 0.f, 0.f};
-  // ring slot j holds particle k0 + j; its successor kDepth ahead is loaded
+  // ring slot j holds particle k0 + j; its successor D ahead is loaded
   // before particle k0 + j is computed
-  for (int k0 = 0; k0 < PPT; k0 += kDepth) {
+#pragma unroll kRingUnroll
+  for (int k0 = 0; k0 < PPT; k0 += D) {
 #pragma unroll
-    for (int j = 0; j < kDepth; ++j) {
+    for (int j = 0; j < D; ++j) {
       const int i = base + (k0 + j) * kThreads + tid;
       const PData<R> cur = ring[j];
-      if (k0 + j + kDepth < PPT) ring[j] = load_particle<R, COMP>(sp, i + kDepth * kThreads, n);
+      if (k0 + j + D < PPT) ring[j] = load_particle<R, COMP>(sp, i + D * kThreads, n);
       push_particle<R, RR, COMP>(a, sp, s, i, cur, dc, acc);
     }
   }
@@ -590,14 +632,16 @@ __device__ __forceinline__ void push_tile(const PushArgs<R>& a, int s, int tile,
       t1 += s_red[1][w];
       t2 += s_red[2][w];
     }
+    // one add per slot and launch, in launch order: deterministic; the
+    // atomic form needs no load, so the work-group retires without waiting
     double* A = a.acc + 4 * (size_t)tile;
-    A[0] += t0;
-    A[1 + s] += t1;
-    A[3] += t2;
+    unsafeAtomicAdd(A + 0, t0);
+    unsafeAtomicAdd(A + 1 + s, t1);
+    unsafeAtomicAdd(A + 3, t2);
   }
 }
 
-template <typename R, int PPT>
+template <typename R, int PPT, int D>
 __device__ __forceinline__ void push_one_tile(const PushArgs<R>& a, int tile,
                                               unsigned long long* lds) {
   const int s = tile < a.tiles0 ? 0 : 1;
@@ -607,11 +651,11 @@ __device__ __forceinline__ void push_one_tile(const PushArgs<R>& a, int tile,
   if (base >= n) return;
   if (s == 0 && a.rr0) {
     if (a.comp)
-      push_tile<R, true, true, PPT>(a, s, tile, n, base, lds);
+      push_tile<R, true, true, PPT, D>(a, s, tile, n, base, lds);
     else
-      push_tile<R, true, false, PPT>(a, s, tile, n, base, lds);
+      push_tile<R, true, false, PPT, D>(a, s, tile, n, base, lds);
   } else {
-    push_tile<R, false, false, PPT>(a, s, tile, n, base, lds);
+    push_tile<R, false, false, PPT, D>(a, s, tile, n, base, lds);
   }
 }
 
@@ -625,7 +669,7 @@ __device__ __forceinline__ void push_one_tile(const PushArgs<R>& a, int tile,
 template <typename R>
 __global__ PIC_PUSH_BOUNDS void k_push(PushArgs<R> a) {
   __shared__ unsigned long long lds[kLdsSlots];
-  push_one_tile<R, kPPT>(a, (int)blockIdx.x, lds);
+  push_one_tile<R, kPPT, kDepth>(a, (int)blockIdx.x, lds);
 }
 
 // ---------------------------------------------------------------- fields
@@ -1058,6 +1102,22 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortArgs<R> p) {
   sort_scatter_block<R>(p, (int)blockIdx.x);
 }
 
+// ---------------------------------------------------------------- self-check
+// Floats with bit patterns first .. first + count - 1 (those >= 1): count the
+// results of sqrt_rn_ge1 and rcp_rn_ge1 (below 2^126) that differ from the
+// correctly rounded sqrtf and 1.0f / x.
+__global__ void k_check_rounding(unsigned first, unsigned count, unsigned long long* bad) {
+  unsigned long long mine = 0;
+  const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+  for (unsigned long long k = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; k < count; k += stride) {
+    const float x = __uint_as_float(first + (unsigned)k);
+    if (!(x >= 1.0f) || !(x <= 3.4028235e38f)) continue;
+    mine += __float_as_uint(sqrt_rn_ge1(x)) != __float_as_uint(sqrtf(x));
+    if (x < 0x1p126f) mine += __float_as_uint(rcp_rn_ge1(x)) != __float_as_uint(1.0f / x);
+  }
+  if (mine) atomicAdd(bad, mine);
+}
+
 // ---------------------------------------------------------------- batched runs
 // One slot per resident run.  Everything a step needs is derived from the
 // run's device step counter n: sort due iff n > 0 and n % K == 0, particle
@@ -1133,7 +1193,7 @@ __global__ PIC_PUSH_BOUNDS void k_push_batch(const SlotDev<R>* __restrict__ slot
   const long long st = uniform(*S.step);
   if (st >= S.target) return;
   const int pp = (int)((st / S.sort_interval) & 1), fp = (int)(st & 1);
-  push_one_tile<R, kBatchPPT>(S.push[pp][fp], b - sr.first(sl), lds);
+  push_one_tile<R, kBatchPPT, kBatchPPT>(S.push[pp][fp], b - sr.first(sl), lds);
 }
 
 template <typename R>

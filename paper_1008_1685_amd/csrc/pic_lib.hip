@@ -922,6 +922,17 @@ pic_status pic_spectrum(pic_run* r, int32_t bins, double e_max, double* host_his
   return PIC_OK;
 }
 
+pic_status pic_check_rounding(uint32_t first, uint32_t count, unsigned long long* d_mismatches,
+                              void* stream) {
+  if (!d_mismatches) return fail(PIC_EINVAL, "null mismatch counter");
+  if ((uint64_t)first + count > 0x100000000ull) return fail(PIC_EINVAL, "bit range past 2^32");
+  if (count == 0) return PIC_OK;
+  const unsigned blocks = std::min<unsigned>(8192u, (count + 255u) / 256u);
+  hipLaunchKernelGGL(k_check_rounding, dim3(blocks), dim3(256), 0, S(stream), first, count, d_mismatches);
+  HIP_TRY(hipGetLastError());
+  return PIC_OK;
+}
+
 pic_status pic_timing_enable(pic_run* r, int32_t period) {
   if (!r) return fail(PIC_EINVAL, "null run");
   if (period < 0) return fail(PIC_EINVAL, "negative timing period");

@@ -55,6 +55,9 @@ def test_workspace_bytes_and_validation_on_host():
 
 def test_null_arguments_are_rejected_without_a_gpu():
     lib = N.load()
+    assert lib.pic_check_rounding(0x3F800000, 16, None, None) == N.PIC_EINVAL
+    cnt = C.c_ulonglong(0)
+    assert lib.pic_check_rounding(0xFFFFFFF0, 32, C.byref(cnt), None) == N.PIC_EINVAL
     assert lib.pic_step(None, 1, None) == N.PIC_EINVAL
     assert lib.pic_diag(None, None, None) == N.PIC_EINVAL
     c = N.PicConfig()
