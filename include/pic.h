@@ -202,12 +202,24 @@ pic_status pic_sort(struct pic_run* run, void* stream);
 
 /* Checkpoint / test I/O of the full state (host buffers).  Blocking.
  * Particle arrays given to pic_get_state must hold `capacity` entries
- * (pic_get_info); removed particles are skipped, so counts are alive counts.
+ * (pic_get_info); removed particles are skipped, so counts are alive counts
+ * (all particle arrays NULL: fields and currents only, count set to 0).
  * pic_set_state validates cells and offsets, replaces the particle arrays
  * (count <= capacity; the current buffers of both parities are cleared when
  * particles are replaced) and/or fields, Ex_int and the current buffers of
  * the current step; step >= 0 also resets the step counter. */
 pic_status pic_get_state(struct pic_run* run, pic_state* st, void* stream);
+
+/* Raw read of particles first .. first + count - 1 of one species (0
+ * electrons, 1 protons) from the current buffers, without compaction:
+ * removed particles keep their slot, with cell = INT32_MIN, until the next
+ * sort.  Indices do not change between sorts, so reads before and after
+ * pic_push_deposit see the same particles.  Copies min(count, n - first)
+ * entries (n: the species' current slot count) into the host arrays of
+ * *out (any may be NULL; residuals exist for FP32 electrons with
+ * compensation only) and sets out->count to that number.  Blocking. */
+pic_status pic_get_particles(struct pic_run* run, int32_t species, int64_t first, int64_t count,
+                             pic_species_state* out, void* stream);
 pic_status pic_set_state(struct pic_run* run, const pic_state* st, void* stream);
 
 /* Ion energy spectrum (Section 4 spectra): weighted histogram of proton

@@ -133,6 +133,8 @@ SIGNATURES = {
     "pic_get_state": (C.c_int, [C.c_void_p, C.POINTER(PicState), C.c_void_p]),
     "pic_set_state": (C.c_int, [C.c_void_p, C.POINTER(PicState), C.c_void_p]),
     "pic_check_rounding": (C.c_int, [C.c_uint32, C.c_uint32, C.c_void_p, C.c_void_p]),
+    "pic_get_particles": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_int64,
+                                    C.POINTER(PicSpeciesState), C.c_void_p]),
     "pic_spectrum": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.POINTER(C.c_double),
                                C.c_void_p]),
     "pic_timing_enable": (C.c_int, [C.c_void_p, C.c_int32]),

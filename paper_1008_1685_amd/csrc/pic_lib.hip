@@ -748,6 +748,34 @@ void pic_free(pic_run* r) {
   delete r;
 }
 
+pic_status pic_get_particles(pic_run* r, int32_t species, int64_t first, int64_t count,
+                             pic_species_state* o, void* stream) {
+  if (!r || !o) return fail(PIC_EINVAL, "null run or output");
+  if (r->batch) return fail(PIC_EBUSY, "run is stepped by a batch; release it first");
+  if (species != 0 && species != 1) return fail(PIC_EINVAL, "species must be 0 or 1");
+  if (first < 0 || count < 0) return fail(PIC_EINVAL, "negative range");
+  hipStream_t s = S(stream);
+  HIP_TRY(hipStreamSynchronize(s));
+  long long n = 0;
+  HIP_TRY(hipMemcpy(&n, r->count + 2 * r->pp + species, sizeof(n), hipMemcpyDeviceToHost));
+  const long long m = std::max(0ll, std::min<long long>(count, n - first));
+  o->count = m;
+  if (!m) return PIC_OK;
+  const SpeciesBuf& b = r->sp[species][r->pp];
+  const size_t rs = rsz(r);
+  auto pull = [&](void* dst, const void* src, size_t es) -> pic_status {
+    if (!dst || !src) return PIC_OK;
+    HIP_TRY(hipMemcpy(dst, static_cast<const char*>(src) + first * es, m * es, hipMemcpyDeviceToHost));
+    return PIC_OK;
+  };
+  pic_status ps;
+  if ((ps = pull(o->cell, b.cell, 4)) || (ps = pull(o->off, b.off, rs)) || (ps = pull(o->ux, b.ux, rs)) ||
+      (ps = pull(o->uy, b.uy, rs)) || (ps = pull(o->uz, b.uz, rs)) || (ps = pull(o->w, b.w, rs)) ||
+      (ps = pull(o->rx, b.rx, 4)) || (ps = pull(o->ry, b.ry, 4)) || (ps = pull(o->rz, b.rz, 4)))
+    return ps;
+  return PIC_OK;
+}
+
 pic_status pic_get_state(pic_run* r, pic_state* st, void* stream) {
   if (!r || !st) return fail(PIC_EINVAL, "null run or state");
   if (r->batch) return fail(PIC_EBUSY, "run is stepped by a batch; release it first");
@@ -761,6 +789,10 @@ pic_status pic_get_state(pic_run* r, pic_state* st, void* stream) {
     pic_species_state& o = st->sp[sp];
     const SpeciesBuf& b = r->sp[sp][r->pp];
     const long long n = cnt[sp];
+    if (!o.cell && !o.off && !o.ux && !o.uy && !o.uz && !o.w && !o.rx && !o.ry && !o.rz) {
+      o.count = 0;  // fields only
+      continue;
+    }
     std::vector<int> cell(n);
     if (n) HIP_TRY(hipMemcpy(cell.data(), b.cell, n * sizeof(int), hipMemcpyDeviceToHost));
     std::vector<long long> idx;

@@ -122,13 +122,19 @@ class Run:
                         + o.E_esc - o.E_in)
         return d
 
-    def get_state(self, residuals: bool = True) -> dict:
+    def get_state(self, residuals: bool = True, particles: bool = True) -> dict:
+        """Fields, currents and (unless particles=False) the alive particles."""
         info = self.get_info()
         n, cap, rdt = info["n_cells"], info["capacity"], self.rdt
+        if not particles:
+            cap = 0
         st = N.PicState()
         out = {}
         keep = []
         for s in range(2):
+            if not particles:
+                out[s] = {}
+                continue
             arrs = dict(cell=np.empty(cap, np.int32), off=np.empty(cap, rdt), ux=np.empty(cap, rdt),
                         uy=np.empty(cap, rdt), uz=np.empty(cap, rdt), w=np.empty(cap, rdt))
             if s == 0 and residuals:
@@ -148,10 +154,28 @@ class Run:
         N.check(self.lib.pic_get_state(self._h, C.byref(st), self._stream()), "pic_get_state")
         res = dict(f)
         res["step"] = st.step
-        for s in range(2):
-            cnt = st.sp[s].count
-            res[f"sp{s}"] = {k: a[:cnt].copy() for k, a in out[s].items()}
+        if particles:
+            for s in range(2):
+                cnt = st.sp[s].count
+                res[f"sp{s}"] = {k: a[:cnt].copy() for k, a in out[s].items()}
         return res
+
+    def get_particles(self, species: int, first: int, count: int, residuals: bool = False,
+                      keys=("cell", "off", "ux", "uy", "uz", "w")) -> dict:
+        """Raw slots first .. first + count - 1 of a species (no compaction;
+        removed particles have cell = INT32_MIN); stable between sorts."""
+        rdt = self.rdt
+        dt = dict(cell=np.int32, off=rdt, ux=rdt, uy=rdt, uz=rdt, w=rdt)
+        arrs = {k: np.empty(count, dt[k]) for k in keys}
+        if residuals:
+            for k in ("rx", "ry", "rz"):
+                arrs[k] = np.empty(count, np.float32)
+        sp = N.PicSpeciesState()
+        for k, a in arrs.items():
+            setattr(sp, k, _ptr(a))
+        N.check(self.lib.pic_get_particles(self._h, int(species), int(first), int(count), C.byref(sp),
+                                           self._stream()), "pic_get_particles")
+        return {k: a[: sp.count] for k, a in arrs.items()}
 
     def set_state(self, particles: dict | None = None, fields: dict | None = None,
                   step: int = -1):

@@ -1,0 +1,124 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py
+times: the precision-form laser-foil run (20,000 cells, 1e7 particles) and
+the stress run (80,000 cells, 2e8 particles), each stepped into the
+laser-foil interaction.  The oracle checks sampled particles one by one (one
+push from the run's own fields, then the contract move from the stored
+momentum, bit-exact); on the whole state the integer charge continuity of
+that push, the integer Gauss law and the particle count are checked."""
+import numpy as np
+import pytest
+
+from oracle import contract, pic as opic, pusher as opush
+from workloads import preset
+
+pytestmark = pytest.mark.gpu
+
+DEAD = np.iinfo(np.int32).min
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    print(f"\n[gpu] {request.node.name}", flush=True)
+    yield
+    torch.cuda.synchronize()
+
+
+def _charge(cell, off, qw, n):
+    """Integer node charge (nodes -1 .. n + 1 at index node + 1)."""
+    q = contract.quantise(off).astype(np.float64)
+    idx = np.asarray(cell, np.int64) + 1
+    w0 = qw * ((1 << 24) - q)
+    w1 = qw * q
+    # float64 sums of integers below 2^53 are exact
+    rho = np.bincount(idx, w0, minlength=n + 3) + np.bincount(idx + 1, w1, minlength=n + 3)
+    return rho[: n + 3].astype(np.int64)
+
+
+def _sampled_push(cfg, run, fields, before, after, s, tol):
+    sim = opic.Pic1D(cfg, init_particles=False)
+    for k in ("Ex", "Ey", "Ez", "By", "Bz"):
+        getattr(sim, k)[:] = fields[k].astype(np.float64)
+    alive = before["cell"] != DEAD
+    xi = before["cell"][alive] + before["off"][alive].astype(np.float64)
+    E, B = sim.gather(xi)
+    u0 = np.stack([before[k][alive] for k in ("ux", "uy", "uz")], 1).astype(np.float64)
+    un, uL = opush.push(u0, E, B, sim.qm[s], sim.dt, sim.eps, sim.rr[s])
+    ug = np.stack([after[k][alive] for k in ("ux", "uy", "uz")], 1).astype(np.float64)
+    if "rx" in after:  # compensated RR: the residual carried into and out of the step
+        ug += np.stack([after[k][alive].astype(np.float64) - before[k][alive] for k in ("rx", "ry", "rz")], 1)
+    nrm = lambda a: np.linalg.norm(a, axis=1)
+    scale = np.maximum.reduce([nrm(u0), nrm(uL), nrm(un), abs(sim.qm[s]) * sim.dt * nrm(E),
+                               nrm(un - uL), np.full(len(u0), 1e-2)])
+    err = float((nrm(ug - un) / scale).max())
+    assert err <= tol, err
+    # contract move from the stored momentum: bit-exact cell and offset
+    c1, o1, *_ = contract.move(before["cell"][alive], before["off"][alive],
+                               after["ux"][alive], after["uy"][alive], after["uz"][alive], cfg["cfl"])
+    inside = (c1 >= 0) & (c1 < sim.nx)
+    assert np.array_equal(after["cell"][alive][inside], c1[inside].astype(np.int32))
+    assert np.array_equal(after["off"][alive][inside], o1[inside])
+    assert np.all(after["cell"][alive][~inside] == DEAD)
+    return int(alive.sum())
+
+
+def _full_size_case(cfg, steps, sample, continuity):
+    from paper_1008_1685_amd import Run
+
+    run = Run(cfg)
+    info = run.get_info()
+    n, cap = info["n_cells"], info["capacity"]
+    assert steps % cfg["sort_interval"] != 0  # no sort in the checked step: slots are stable
+    run.step(steps)
+    d0 = run.diag()
+    assert d0["gauss_int"] == 0 and not d0["nonfinite"]
+    n_slots = [int(c) for c in d0["n_alive"]]
+    fields = run.get_state(particles=False)
+    comp = cfg["precision"] == "fp32" and cfg["rr"] and cfg["rr_compensated"]
+    rng = np.random.default_rng(7)
+    picks, before = {}, {}
+    for s in range(2):
+        # a contiguous window of slots at a random place in the (sorted) species
+        picks[s] = int(rng.integers(0, max(1, n_slots[s] - sample)))
+        before[s] = run.get_particles(s, picks[s], sample, residuals=(s == 0 and comp))
+    # every slot (alive or removed since the last sort): reads stop at the slot count
+    full0 = {s: run.get_particles(s, 0, cap, keys=("cell", "off")) for s in range(2)} if continuity else None
+    run.push_deposit()
+    after = {s: run.get_particles(s, picks[s], sample, residuals=(s == 0 and comp)) for s in range(2)}
+    checked = 0
+    for s in range(2):
+        checked += _sampled_push(cfg, run, fields, before[s], after[s], s, 1e-5)
+    assert checked > sample  # both species sampled
+    if continuity:
+        st = run.get_state(particles=False)
+        total = np.zeros(n + 3, np.int64)
+        for s, Z in ((0, -1), (1, 1)):
+            b = full0[s]
+            a = run.get_particles(s, 0, cap, keys=("ux", "uy", "uz"))
+            assert len(a["ux"]) == len(b["cell"])
+            alive = b["cell"] != DEAD
+            c1, o1, *_ = contract.move(b["cell"][alive], b["off"][alive], a["ux"][alive], a["uy"][alive],
+                                       a["uz"][alive], cfg["cfl"])
+            qw = Z * 256
+            total += _charge(c1, o1, qw, n) - _charge(b["cell"][alive], b["off"][alive], qw, n)
+        div = np.zeros(n + 3, np.int64)
+        div[: n + 2] += st["Jx_int"]
+        div[1:] -= st["Jx_int"]
+        assert np.array_equal(total + div, np.zeros_like(total))
+    run.field_advance()
+    d1 = run.diag()
+    assert d1["gauss_int"] == 0 and not d1["nonfinite"]
+    assert d1["step"] == steps + 1
+    run.close()
+
+
+def test_precision_form_full_size_step_matches_oracle():
+    # 1e7 particles, 20,000 cells; the pulse reaches the foil after 3,200 steps
+    _full_size_case(preset("c3"), steps=3601, sample=200_000, continuity=True)
+
+
+def test_stress_form_full_size_step_matches_oracle():
+    # 2e8 particles, 80,000 cells, a0 = 800; the pulse reaches the foil after 6,400 steps
+    _full_size_case(preset("c5"), steps=6417, sample=200_000, continuity=True)
