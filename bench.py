@@ -127,6 +127,61 @@ def serve_bench(n_runs=256, rate=20.0, seed=0, max_slots=64, budget_gb=64.0):
                 peak_resident_bytes=srv.peak_bytes, max_slots=max_slots, failed_checks=bad)
 
 
+def stress_bench(serve_kwargs, warm=400, window=200, chunk=8, share=0.2):
+    """The stress run (2e8 particles, 80,000 cells, LP a0 = 800) on its own
+    stream: its throughput alone, then stepped by a second host thread while
+    the serving stream is served on the same GPU (latency under load).  Both
+    streams have the default priority; the stress thread keeps a duty cycle
+    of `share` (after a chunk of steps that took t it waits t (1 - share) /
+    share), which leaves the rest of the GPU time to the latency-bound
+    requests (share = 1: no throttling)."""
+    import threading
+
+    import torch
+
+    from paper_1008_1685_amd import Run
+    from workloads import preset
+
+    cfg = preset("c5")
+    st = torch.cuda.Stream()
+    run = Run(cfg, stream=st)
+    n = sum(run.get_info()["n_init"])
+    run.step(warm)
+    st.synchronize()
+    t0 = time.perf_counter()
+    run.step(window)
+    st.synchronize()
+    alone = n * window / (time.perf_counter() - t0)
+    stop = threading.Event()
+    done = [0]
+
+    def loop():
+        while not stop.is_set():
+            ta = time.perf_counter()
+            run.step(chunk)
+            st.synchronize()
+            done[0] += chunk
+            if share < 1.0:
+                stop.wait((time.perf_counter() - ta) * (1.0 - share) / share)
+
+    th = threading.Thread(target=loop, daemon=True)
+    t1 = time.perf_counter()
+    th.start()
+    try:
+        serving = serve_bench(**serve_kwargs)
+    finally:
+        stop.set()
+        th.join()
+    el = time.perf_counter() - t1
+    d = run.diag()
+    run.close()
+    return dict(workload=f"c5: LP a0={cfg['a0']:g}, {run.info['n_init'][0] + run.info['n_init'][1]} particles, "
+                         f"80000 cells, fp32 + compensated RR, stepped from step {warm}",
+                pushes_per_s_alone=alone, duty_cycle=share, pushes_per_s_with_serving=n * done[0] / el,
+                steps_with_serving=done[0], gauss_int=d["gauss_int"],
+                serving_under_load=serving)
+
+
 def write_traffic(fetch, write, cfetch, cwrite, out_path):
     """profiles/traffic.json from rocprofv3 counter_collection.csv files:
     FETCH_SIZE and WRITE_SIZE of this benchmark (--steps 50 --warmup 3950
@@ -164,6 +219,12 @@ def main():
     ap.add_argument("--no-side-runs", action="store_true",
                     help="skip the RR-off and FP64 comparison runs and the CPU baseline")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-form measurement")
+    ap.add_argument("--no-stress", action="store_true",
+                    help="skip the stress run and the serving measurement under its load")
+    ap.add_argument("--stress-only", type=int, default=0, metavar="N",
+                    help="only run the stress run with the first N serving requests beside it")
+    ap.add_argument("--stress-share", type=float, default=0.2,
+                    help="duty cycle of the stress run while requests are served (1: unthrottled)")
     ap.add_argument("--serve-only", type=int, default=0, metavar="N",
                     help="only run the serving measurement, on the first N requests")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
@@ -186,6 +247,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.serve_only:
         print(json.dumps(dict(serving=serve_bench(n_runs=args.serve_only))), flush=True)
+        return
+    if args.stress_only:
+        print(json.dumps(dict(stress=stress_bench(dict(n_runs=args.stress_only), share=args.stress_share))),
+              flush=True)
         return
     cfg = preset(args.workload)
     res = time_run(cfg, args.steps, args.warmup, args.diag_every)
@@ -244,6 +309,8 @@ def main():
         line["cpu_baseline"] = cpu_baseline(cfg)
     if not args.no_serve:
         line["serving"] = serve_bench()
+        if not args.no_stress:
+            line["stress"] = stress_bench(dict(), share=args.stress_share)
     print(json.dumps(line), flush=True)
 
 
