@@ -23,8 +23,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-# per-kernel durations come from HIP events around every TIMING_PERIOD-th
-# launch of each kernel kind (events around every launch add queue time)
+# per-kernel durations come from HIP events recorded by every
+# TIMING_PERIOD-th launch of each kernel kind at its start and end
 TIMING_PERIOD = 8
 
 
@@ -293,7 +293,7 @@ def main():
         kernel_us_per_launch={k: v[0] * 1e3 / max(v[1], 1) for k, v in res["kernels"].items()},
         kernel_ms_per_step={k: v[0] / max(v[1], 1) * (1.0 / cfg["sort_interval"] if k == "sort" else 1.0)
                             for k, v in res["kernels"].items()},
-        timing=f"HIP events around every {TIMING_PERIOD}th launch of each kernel",
+        timing=f"HIP start/end events of every {TIMING_PERIOD}th launch of each kernel",
         energy_balance=res["diag1"]["balance"] / max(res["diag1"]["E_in"], 1e-300),
         gauss_int=res["diag1"]["gauss_int"],
     )

@@ -240,11 +240,11 @@ pic_status pic_spectrum(struct pic_run* run, int32_t bins, double e_max_mev,
 pic_status pic_check_rounding(uint32_t first, uint32_t count, unsigned long long* d_mismatches,
                               void* stream);
 
-/* Per-kernel timing for profiling: with period p > 0, pic_step records HIP
- * events around every p-th launch of each kernel kind (p = 1: every launch;
- * an event pair costs several microseconds of queue time, so sampling keeps
- * the timed steps close to untimed ones); p = 0 turns timing off and
- * p < 0 is PIC_EINVAL.  pic_timing_read synchronises the stream and returns
+/* Per-kernel timing for profiling: with period p > 0, every p-th launch of
+ * each kernel kind records a HIP event pair at its own start and end
+ * (hipExtLaunchKernel), so the time is the kernel's execution (for the sort,
+ * from the start of its first pass to the end of its last); p = 1 times
+ * every launch, p = 0 turns timing off and p < 0 is PIC_EINVAL.  pic_timing_read synchronises the stream and returns
  * the accumulated milliseconds and the number of timed launches for kernel
  * k = 0 push-deposit, 1 field advance, 2 sort (all passes). */
 pic_status pic_timing_enable(struct pic_run* run, int32_t period);

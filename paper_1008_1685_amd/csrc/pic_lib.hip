@@ -4,6 +4,7 @@
 #include "kernels.hpp"
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cmath>
@@ -219,8 +220,12 @@ hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 constexpr size_t kNoEvent = ~(size_t)0;
 
-pic_status ev_begin(pic_run* r, int kind, hipStream_t st, size_t* slot) {
+// Events for a sampled launch: the kernel launch itself records them at its
+// start and end (hipExtLaunchKernel), so the measured time is the kernel's
+// execution without the queue time of separate event packets.
+pic_status ev_pick(pic_run* r, int kind, size_t* slot, hipEvent_t* a, hipEvent_t* b) {
   *slot = kNoEvent;
+  *a = *b = nullptr;
   if (!r->timing) return PIC_OK;
   if (r->seen[kind]++ % r->timing) return PIC_OK;  // not sampled
   if (r->ev.empty()) {
@@ -240,19 +245,18 @@ pic_status ev_begin(pic_run* r, int kind, hipStream_t st, size_t* slot) {
     e.used = false;
   }
   e.kind = kind;
-  HIP_TRY(hipEventRecord(e.a, st));
   *slot = r->ev_next;
+  *a = e.a;
+  *b = e.b;
   r->ev_next = (r->ev_next + 1) % r->ev.size();
   return PIC_OK;
 }
 
-pic_status ev_end(pic_run* r, hipStream_t st, size_t slot) {
-  if (slot == kNoEvent) return PIC_OK;
+void ev_done(pic_run* r, size_t slot) {
+  if (slot == kNoEvent) return;
   TimingRec& e = r->ev[slot];
-  HIP_TRY(hipEventRecord(e.b, st));
   e.used = true;
   r->launches[e.kind] += 1;
-  return PIC_OK;
 }
 
 bool comp_on(const pic_run* r) {
@@ -347,24 +351,26 @@ template <typename R>
 pic_status launch_push(pic_run* r, hipStream_t st) {
   const PushArgs<R> a = make_push_args<R>(r, r->pp, (int)(r->step & 1));
   if (a.ntiles == 0) return PIC_OK;
-  size_t slot = 0;
-  pic_status ps = ev_begin(r, 0, st, &slot);
+  size_t slot;
+  hipEvent_t e0, e1;
+  pic_status ps = ev_pick(r, 0, &slot, &e0, &e1);
   if (ps) return ps;
-  hipLaunchKernelGGL(k_push<R>, dim3(a.ntiles), dim3(kThreads), 0, st, a);
+  hipExtLaunchKernelGGL(k_push<R>, dim3(a.ntiles), dim3(kThreads), 0, st, e0, e1, 0, a);
   HIP_TRY(hipGetLastError());
-  return ev_end(r, st, slot);
+  ev_done(r, slot);
+  return PIC_OK;
 }
 
 template <typename R>
 pic_status launch_field(pic_run* r, hipStream_t st) {
   const FieldArgs<R> f = make_field_args<R>(r, (int)(r->step & 1), 1);
-  size_t slot = 0;
-  pic_status ps = ev_begin(r, 1, st, &slot);
+  size_t slot;
+  hipEvent_t e0, e1;
+  pic_status ps = ev_pick(r, 1, &slot, &e0, &e1);
   if (ps) return ps;
-  hipLaunchKernelGGL(k_field<R>, dim3(field_blocks_for(r)), dim3(kFieldChunk), 0, st, f);
+  hipExtLaunchKernelGGL(k_field<R>, dim3(field_blocks_for(r)), dim3(kFieldChunk), 0, st, e0, e1, 0, f);
   HIP_TRY(hipGetLastError());
-  ps = ev_end(r, st, slot);
-  if (ps) return ps;
+  ev_done(r, slot);
   r->step += 1;
   return PIC_OK;
 }
@@ -373,16 +379,17 @@ template <typename R>
 pic_status launch_sort(pic_run* r, hipStream_t st) {
   const SortArgs<R> p = make_sort_args<R>(r, r->pp);
   const int grid = p.blocks0 + sort_blocks_for(r->n_max[1]);
-  size_t slot = 0;
-  pic_status ps = ev_begin(r, 2, st, &slot);
+  size_t slot;
+  hipEvent_t e0, e1;
+  pic_status ps = ev_pick(r, 2, &slot, &e0, &e1);
   if (ps) return ps;
-  hipLaunchKernelGGL(k_sort_hist<R>, dim3(grid), dim3(kSortThreads), 0, st, p);
+  // the events span the three passes: start of the histogram, end of the scatter
+  hipExtLaunchKernelGGL(k_sort_hist<R>, dim3(grid), dim3(kSortThreads), 0, st, e0, nullptr, 0, p);
   hipLaunchKernelGGL(k_sort_scan, dim3(2), dim3(1024), 0, st, r->cnt[0], r->cnt[1], r->cursor[0],
                      r->cursor[1], r->count + 2 * (r->pp ^ 1), r->d.nx);
-  hipLaunchKernelGGL(k_sort_scatter<R>, dim3(grid), dim3(kSortThreads), 0, st, p);
+  hipExtLaunchKernelGGL(k_sort_scatter<R>, dim3(grid), dim3(kSortThreads), 0, st, nullptr, e1, 0, p);
   HIP_TRY(hipGetLastError());
-  ps = ev_end(r, st, slot);
-  if (ps) return ps;
+  ev_done(r, slot);
   r->pp ^= 1;
   return PIC_OK;
 }
