@@ -12,10 +12,12 @@ on Radiation Pressure Acceleration"):
                  Eq. (f_r), combined by the leapfrog splitting of
                  Eqs. (tot)-(estimgamma), Section 3; friction coefficient d of
                  Eq. (damping) and the lab-frame LL force of Eq. (3dLL).
-* ``analytic`` - exact plane-wave orbits without RR and with the
-                 non-derivative LL force (Section 2 and the single-electron
-                 test of Section 3), uniform-field gyration and radiative
-                 cooling closed forms.
+* ``analytic`` - exact plane-wave orbits without RR, with the
+                 non-derivative LL force and with the complete Eq. (3dLL)
+                 (Section 2 and the single-electron test of Section 3),
+                 uniform-field gyration and radiative cooling closed forms.
+* ``rk4``      - classical Runge-Kutta single-electron integrator, the
+                 comparator of the single-particle tests of Section 3.
 * ``contract`` - the integer (fixed-point) current-deposition contract,
                  evaluated in float32 exactly as the GPU stores its state.
 * ``pic``      - a plain 1D3V PIC loop (laser-foil problem of Section 4)

@@ -18,7 +18,15 @@ integrates) the equations reduce to quadratures:
   u_x = (1 + u_perp^2 - h^2) / (2 h),  dt/dphi = gamma / h,  dx/dphi = u_x / h.
 
 With eps = 0 this is the textbook Lorentz orbit (h conserved, u_perp =
-u_perp0 + A - A0).  The derivation uses only f_L x B + (v.E) E =
+u_perp0 + A - A0).
+
+The complete Eq. (3dLL) adds -eps gamma [D E + v x D B], D = d/dt + v.grad
+the total derivative along the orbit.  In a plane wave D F = (1 - v_x) F'
+(prime: d/dphi), so the term is -eps h [E' + v x B']: it does no work on
+h (dh/dphi unchanged) and adds -eps h E_perp' to du_perp/dphi, hence
+-eps E_perp' to d(u_perp/h)/dphi.  The complete solution therefore has the
+extra term -eps h0 (E_perp(phi) - E_perp(phi0)) inside the bracket of
+u_perp, with h as above (``full_ll``).  The derivation uses only f_L x B + (v.E) E =
 (1 - v_x) E_perp^2 x_hat and gamma^2 [F^2 - (v.E)^2] = h^2 E_perp^2 for a
 plane wave; both identities are checked numerically in the tests.  The
 quadratures are integrated by an adaptive 8th-order method at 1e-13
@@ -51,6 +59,21 @@ class MonochromaticWave:
         ph = phi + self.psi
         return np.array([-self.ay * np.cos(ph), self.az * np.sin(ph)])
 
+    def dE(self, phi):
+        """dE_perp/dphi."""
+        ph = phi + self.psi
+        return np.array([self.ay * np.sin(ph), self.az * np.cos(ph)])
+
+    def partials(self, x, t):
+        """(dE/dt, dE/dx, dB/dt, dB/dx) in the lab frame at (x, t), each of
+        shape (..., 3): a function of phi = t - x, so d/dx = -d/dt."""
+        phi = np.asarray(t - x, dtype=np.float64)
+        dp = self.dE(phi)
+        zero = np.zeros_like(phi)
+        Et = np.stack([zero, dp[0], dp[1]], axis=-1)
+        Bt = np.stack([zero, -dp[1], dp[0]], axis=-1)
+        return Et, -Et, Bt, -Bt
+
     def fields(self, x, t):
         """Lab-frame E and B (shape (..., 3)) at position x and time t."""
         phi = np.asarray(t - x, dtype=np.float64)
@@ -62,18 +85,20 @@ class MonochromaticWave:
 
 
 class PlaneWaveOrbit:
-    """Exact electron orbit in a plane wave, Lorentz plus non-derivative LL.
+    """Exact electron orbit in a plane wave, Lorentz plus the non-derivative
+    LL terms (``full_ll``: plus the derivative term as well).
 
     Initial condition: position x0 and momentum u0 at time t0."""
 
-    def __init__(self, wave, u0, x0=0.0, t0=0.0, eps=0.0, phi_span=200.0):
-        self.w, self.eps = wave, float(eps)
+    def __init__(self, wave, u0, x0=0.0, t0=0.0, eps=0.0, phi_span=200.0, full_ll=False):
+        self.w, self.eps, self.full = wave, float(eps), bool(full_ll)
         u0 = np.asarray(u0, dtype=np.float64)
         self.phi0 = t0 - x0
         g0 = np.sqrt(1.0 + u0 @ u0)
         self.h0 = g0 - u0[0]
         self.up0 = u0[1:].copy()
         self.A0 = wave.A(self.phi0)
+        self.E0 = wave.E(self.phi0)
         y0 = np.array([0.0, 0.0, 0.0, t0, x0])
         kw = dict(method="DOP853", rtol=1e-13, atol=1e-13, dense_output=True)
         self.fwd = solve_ivp(self._rhs, (self.phi0, self.phi0 + phi_span), y0, **kw)
@@ -83,7 +108,10 @@ class PlaneWaveOrbit:
 
     def _state(self, phi, I, K):
         h = 1.0 / (1.0 / self.h0 + self.eps * I)
-        up = (h / self.h0) * (self.up0 + self.w.A(phi) - self.A0 - self.eps * self.h0 * K)
+        br = self.up0 + self.w.A(phi) - self.A0 - self.eps * self.h0 * K
+        if self.full:
+            br = br - self.eps * self.h0 * (self.w.E(phi) - self.E0)
+        up = (h / self.h0) * br
         ux = (1.0 + up @ up - h * h) / (2.0 * h)
         return h, ux, up
 

@@ -70,7 +70,19 @@ def rr_force(E, B, p, eps):
                    + (g * g * bracket)[..., None] * v)
 
 
-def push(u_old, E, B, qm, dt, eps, rr):
+def derivative_force(Et, Ex, Bt, Bx, p, eps):
+    """The derivative term of Eq. (3dLL) for an electron with momentum p:
+    -eps gamma [D E + v x D B], D = d/dt + v_x d/dx (fields of x and t only,
+    as on the 1D grid), from the partial derivatives at the particle."""
+    g = gamma_of(p)
+    v = p / g[..., None]
+    vx = v[..., :1]
+    DE = Et + vx * Ex
+    DB = Bt + vx * Bx
+    return -eps * g[..., None] * (DE + np.cross(v, DB))
+
+
+def push(u_old, E, B, qm, dt, eps, rr, partials=None):
     """One leapfrog momentum step of the paper's scheme (Section 3).
 
     1. Lorentz part by Boris: u_L^{n+1/2} (Eq. (part1), left).
@@ -79,12 +91,24 @@ def push(u_old, E, B, qm, dt, eps, rr):
     3. u^{n+1/2} = u_L^{n+1/2} + f_R^(n) dt with f_R from Eq. (f_r) at the
        fields E^(n), B^(n) (Eq. (pertfull)).
 
+    With ``partials`` = (dE/dt, dE/dx, dB/dt, dB/dx) at the particle the
+    derivative term of Eq. (3dLL) is added to f_R, evaluated at the same
+    p^(n) (the complete LL force of the paper's single-particle tests).
+
     Returns (u_new, u_L).  With ``rr`` false (or eps = 0) u_new = u_L."""
     uL = boris(u_old, E, B, qm, dt)
     if not rr:
         return uL, uL
     p_mid = 0.5 * (uL + u_old)
-    return uL + dt * rr_force(E, B, p_mid, eps), uL
+    f = rr_force(E, B, p_mid, eps)
+    if partials is not None:
+        f = f + derivative_force(*partials, p_mid, eps)
+    return uL + dt * f, uL
+
+
+def ll_full(E, B, partials, u, eps):
+    """Right-hand side of the complete Eq. (3dLL) for an electron."""
+    return ll_nonderivative(E, B, u, eps) + derivative_force(*partials, u, eps)
 
 
 def ll_nonderivative(E, B, u, eps):
