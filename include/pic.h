@@ -229,6 +229,37 @@ pic_status pic_set_state(struct pic_run* run, const pic_state* st, void* stream)
 pic_status pic_spectrum(struct pic_run* run, int32_t bins, double e_max_mev,
                         double* host_hist, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Test electrons in a given plane wave (the single-particle tests of
+ * Section 3): independent of any run.  The wave travels along +x with
+ * A_y = a_y sin(phi + psi), A_z = a_z cos(phi + psi), phi = t - x,
+ * E = (0, -dA_y/dphi, -dA_z/dphi), B = (0, -E_z, E_y) (a_z = 0: linear
+ * polarisation); units as in the runs.
+ * scheme PIC_TRACK_LEAPFROG: the pusher of the runs (Boris plus the RR
+ *   step of Eqs. (estim1)-(pertfull)); on entry x = x^0 at time t0 and
+ *   u = u^{-1/2}, on return x^{steps} and u^{steps - 1/2}.  FP32 adds the
+ *   RR increment by TwoSum as the runs do; the returned u includes the
+ *   carried residual.
+ * scheme PIC_TRACK_RK4: classical fourth-order Runge-Kutta of Eq. (3dLL),
+ *   x and u both at t0 on entry and at t0 + steps dt on return.
+ * rr: PIC_RR_OFF (Lorentz force), PIC_RR_REDUCED (plus the non-derivative
+ *   terms of Eq. (3dLL), i.e. Eq. (f_r): the force of the runs), PIC_RR_FULL
+ *   (plus the derivative term, with the wave's exact field derivatives).
+ * precision: arithmetic of the momentum step (positions and phases FP64).
+ * d_x, d_ux, d_uy, d_uz: device arrays of n doubles (x: position along the
+ * propagation direction), updated in place.  Asynchronous on stream; invalid
+ * arguments return PIC_EINVAL before any launch. */
+typedef struct pic_wave {
+  double a_y, a_z, psi;
+} pic_wave;
+
+enum { PIC_TRACK_LEAPFROG = 0, PIC_TRACK_RK4 = 1 };
+enum { PIC_RR_OFF = 0, PIC_RR_REDUCED = 1, PIC_RR_FULL = 2 };
+
+pic_status pic_track(const pic_wave* wave, int32_t scheme, int32_t rr, int32_t precision,
+                     double lambda_um, double dt, double t0, int64_t steps, int64_t n, double* d_x,
+                     double* d_ux, double* d_uy, double* d_uz, void* stream);
+
 /* Self-check of the move arithmetic (the correctly rounded square root and
  * reciprocal of the deposition contract are computed from hardware estimates
  * plus FMA corrections): for every float whose bit pattern lies in

@@ -86,6 +86,14 @@ class PicDiagOut(C.Structure):
     ]
 
 
+class PicWave(C.Structure):
+    _fields_ = [("a_y", C.c_double), ("a_z", C.c_double), ("psi", C.c_double)]
+
+
+PIC_TRACK_LEAPFROG, PIC_TRACK_RK4 = 0, 1
+PIC_RR_OFF, PIC_RR_REDUCED, PIC_RR_FULL = 0, 1, 2
+
+
 class PicSpeciesState(C.Structure):
     _fields_ = [
         ("count", C.c_int64),
@@ -133,6 +141,9 @@ SIGNATURES = {
     "pic_get_state": (C.c_int, [C.c_void_p, C.POINTER(PicState), C.c_void_p]),
     "pic_set_state": (C.c_int, [C.c_void_p, C.POINTER(PicState), C.c_void_p]),
     "pic_check_rounding": (C.c_int, [C.c_uint32, C.c_uint32, C.c_void_p, C.c_void_p]),
+    "pic_track": (C.c_int, [C.POINTER(PicWave), C.c_int32, C.c_int32, C.c_int32, C.c_double,
+                            C.c_double, C.c_double, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
+                            C.c_void_p, C.c_void_p, C.c_void_p]),
     "pic_get_particles": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_int64,
                                     C.POINTER(PicSpeciesState), C.c_void_p]),
     "pic_spectrum": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.POINTER(C.c_double),

@@ -372,6 +372,111 @@ struct PData {
   float rx, ry, rz;
 };
 
+// Partial derivatives of the fields at a particle, for the derivative term of
+// Eq. (3dLL): d/dt and d/dx of E_x, E_y, E_z, B_y, B_z (B_x = 0 in 1D).
+template <typename R>
+struct FieldRates {
+  R etx, ety, etz, bty, btz;  // d/dt
+  R exx, exy, exz, bxy, bxz;  // d/dx
+};
+
+template <typename R>
+struct MomentumOut {
+  R Lx, Ly, Lz;     // u_L^{n+1/2}, after the Boris step
+  R nx, ny, nz;     // u^{n+1/2} as stored
+  R ddx, ddy, ddz;  // the RR increment added (with the carried residual under COMP)
+  R gL;             // gamma of u_L (RR only)
+};
+
+// One momentum step of the paper's scheme (Section 3): Boris for the Lorentz
+// force (Eq. (part1)), then the RR increment dt f_R of Eq. (f_r) at the
+// mid-step estimate p^(n) = (u_L + u^{n-1/2}) / 2 of Eqs. (estim1) and
+// (estimgamma), added as in Eq. (pertfull).  qh = q dt / (2 m), k = eps dt.
+// COMP adds the increment by TwoSum and carries the FP32 rounding residual
+// in (rx, ry, rz).  DERIV adds the derivative term of Eq. (3dLL) at the same
+// p^(n) (the complete LL force, for tracking in given fields).
+template <typename R, bool RR, bool COMP, bool DERIV>
+__device__ __forceinline__ void momentum_step(R ux, R uy, R uz, R ex, R ey, R ez, R by, R bz, R qh,
+                                              R k, const FieldRates<R>& fr, float& rx, float& ry,
+                                              float& rz, float& stiff, MomentumOut<R>& o) {
+  // Boris (B_x = 0 in 1D)
+  const R hx = qh * ex, hy = qh * ey, hz = qh * ez;
+  const R mx = ux + hx, my = uy + hy, mz = uz + hz;
+  const R igm = rsq(R(1) + mx * mx + my * my + mz * mz);
+  const R ty = qh * by * igm, tz = qh * bz * igm;
+  const R sf = R(2) * rcp(R(1) + ty * ty + tz * tz);
+  const R px = mx + (my * tz - mz * ty);
+  const R py = my - mx * tz;
+  const R pz = mz + mx * ty;
+  const R sy = sf * ty, sz = sf * tz;
+  const R Lx = mx + (py * sz - pz * sy) + hx;
+  const R Ly = my - px * sz + hy;
+  const R Lz = mz + px * sy + hz;
+
+  R nx = Lx, ny = Ly, nz = Lz;
+  R gL = R(0), ddx = R(0), ddy = R(0), ddz = R(0);
+  if (RR) {
+    // mid-step momentum (u_L + u^{n-1/2}) / 2 and its velocity
+    const R qx = R(0.5) * (Lx + ux), qy = R(0.5) * (Ly + uy), qz = R(0.5) * (Lz + uz);
+    const R g2 = R(1) + qx * qx + qy * qy + qz * qz;
+    const R ig = rsq(g2);
+    const R vx = qx * ig, vy = qy * ig, vz = qz * ig;
+    // F = E + v x B = -f_L
+    const R Fx = ex + (vy * bz - vz * by);
+    const R Fy = ey - vx * bz;
+    const R Fz = ez + vx * by;
+    const R vE = vx * ex + vy * ey + vz * ez;
+    R br = Fx * Fx + Fy * Fy + Fz * Fz - vE * vE;
+    br = br > R(0) ? br : R(0);
+    const R g2b = g2 * br;
+    // dt f_R = dt eps [F x B + (v.E) E - gamma^2 (F^2 - (v.E)^2) v]
+    ddx = k * ((Fy * bz - Fz * by) + vE * ex - g2b * vx);
+    ddy = k * (vE * ey - Fx * bz - g2b * vy);
+    ddz = k * (Fx * by + vE * ez - g2b * vz);
+    if (DERIV) {
+      // derivative term of Eq. (3dLL): -eps gamma [D E + v x D B], D = d/dt + v_x d/dx
+      const R g = g2 * ig;
+      const R DEx = fr.etx + vx * fr.exx, DEy = fr.ety + vx * fr.exy, DEz = fr.etz + vx * fr.exz;
+      const R DBy = fr.bty + vx * fr.bxy, DBz = fr.btz + vx * fr.bxz;
+      ddx -= k * g * (DEx + (vy * DBz - vz * DBy));
+      ddy -= k * g * (DEy - vx * DBz);
+      ddz -= k * g * (DEz + vx * DBy);
+    }
+    if (ddx * ddx + ddy * ddy + ddz * ddz > R(0.01) * (Lx * Lx + Ly * Ly + Lz * Lz)) stiff += 1.f;
+    if (COMP) {
+      // increment plus the residual carried from earlier steps, added by TwoSum;
+      // the new rounding residual is carried to the next step
+      const float dpx = (float)ddx + rx, dpy = (float)ddy + ry, dpz = (float)ddz + rz;
+      float sxx, syy, szz;
+      two_sum((float)Lx, dpx, sxx, rx);
+      two_sum((float)Ly, dpy, syy, ry);
+      two_sum((float)Lz, dpz, szz, rz);
+      ddx = dpx;
+      ddy = dpy;
+      ddz = dpz;
+      nx = sxx;
+      ny = syy;
+      nz = szz;
+    } else {
+      nx = Lx + ddx;
+      ny = Ly + ddy;
+      nz = Lz + ddz;
+    }
+    gL = fsqrt(R(1) + Lx * Lx + Ly * Ly + Lz * Lz);
+  }
+
+  o.Lx = Lx;
+  o.Ly = Ly;
+  o.Lz = Lz;
+  o.nx = nx;
+  o.ny = ny;
+  o.nz = nz;
+  o.ddx = ddx;
+  o.ddy = ddy;
+  o.ddz = ddz;
+  o.gL = gL;
+}
+
 // All loads of one particle are independent of each other, so a thread keeps
 // several particles' loads in flight while it computes an earlier one.
 // Past the end of the species (i >= n, last tile only) the loads read
@@ -426,64 +531,12 @@ __device__ __forceinline__ void push_particle(const PushArgs<R>& a, const Specie
   const R by = fn * h0.by + fh * h1.by;
   const R bz = fn * h0.bz + fh * h1.bz;
 
-  // ---- Boris (B_x = 0 in 1D)
-  const R qh = a.qh[s];
-  const R hx = qh * ex, hy = qh * ey, hz = qh * ez;
-  const R mx = ux + hx, my = uy + hy, mz = uz + hz;
-  const R igm = rsq(R(1) + mx * mx + my * my + mz * mz);
-  const R ty = qh * by * igm, tz = qh * bz * igm;
-  const R sf = R(2) * rcp(R(1) + ty * ty + tz * tz);
-  const R px = mx + (my * tz - mz * ty);
-  const R py = my - mx * tz;
-  const R pz = mz + mx * ty;
-  const R sy = sf * ty, sz = sf * tz;
-  const R Lx = mx + (py * sz - pz * sy) + hx;
-  const R Ly = my - px * sz + hy;
-  const R Lz = mz + px * sy + hz;
-
-  R nx = Lx, ny = Ly, nz = Lz;
-  R gL = R(0), ddx = R(0), ddy = R(0), ddz = R(0);
-  if (RR) {
-    // mid-step momentum (u_L + u^{n-1/2}) / 2 and its velocity
-    const R qx = R(0.5) * (Lx + ux), qy = R(0.5) * (Ly + uy), qz = R(0.5) * (Lz + uz);
-    const R g2 = R(1) + qx * qx + qy * qy + qz * qz;
-    const R ig = rsq(g2);
-    const R vx = qx * ig, vy = qy * ig, vz = qz * ig;
-    // F = E + v x B = -f_L
-    const R Fx = ex + (vy * bz - vz * by);
-    const R Fy = ey - vx * bz;
-    const R Fz = ez + vx * by;
-    const R vE = vx * ex + vy * ey + vz * ez;
-    R br = Fx * Fx + Fy * Fy + Fz * Fz - vE * vE;
-    br = br > R(0) ? br : R(0);
-    const R g2b = g2 * br;
-    const R k = a.eps * a.dt;
-    // dt f_R = dt eps [F x B + (v.E) E - gamma^2 (F^2 - (v.E)^2) v]
-    ddx = k * ((Fy * bz - Fz * by) + vE * ex - g2b * vx);
-    ddy = k * (vE * ey - Fx * bz - g2b * vy);
-    ddz = k * (Fx * by + vE * ez - g2b * vz);
-    if (ddx * ddx + ddy * ddy + ddz * ddz > R(0.01) * (Lx * Lx + Ly * Ly + Lz * Lz)) acc.stiff += 1.f;
-    if (COMP) {
-      // increment plus the residual carried from earlier steps, added by TwoSum;
-      // the new rounding residual is carried to the next step
-      const float dpx = (float)ddx + rx, dpy = (float)ddy + ry, dpz = (float)ddz + rz;
-      float sxx, syy, szz;
-      two_sum((float)Lx, dpx, sxx, rx);
-      two_sum((float)Ly, dpy, syy, ry);
-      two_sum((float)Lz, dpz, szz, rz);
-      ddx = dpx;
-      ddy = dpy;
-      ddz = dpz;
-      nx = sxx;
-      ny = syy;
-      nz = szz;
-    } else {
-      nx = Lx + ddx;
-      ny = Ly + ddy;
-      nz = Lz + ddz;
-    }
-    gL = fsqrt(R(1) + Lx * Lx + Ly * Ly + Lz * Lz);
-  }
+  MomentumOut<R> mo;
+  momentum_step<R, RR, COMP, false>(ux, uy, uz, ex, ey, ez, by, bz, a.qh[s], a.eps * a.dt,
+                                    FieldRates<R>{}, rx, ry, rz, acc.stiff, mo);
+  const R Lx = mo.Lx, Ly = mo.Ly, Lz = mo.Lz;
+  const R nx = mo.nx, ny = mo.ny, nz = mo.nz;
+  const R ddx = mo.ddx, ddy = mo.ddy, ddz = mo.ddz, gL = mo.gL;
 
   // ---- move (contract arithmetic)
   R g, vy, vz, o1, shift;
@@ -1100,6 +1153,140 @@ __device__ __forceinline__ void sort_scatter_block(const SortArgs<R>& p, int blk
 template <typename R>
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortArgs<R> p) {
   sort_scatter_block<R>(p, (int)blockIdx.x);
+}
+
+// ---------------------------------------------------------------- test electrons
+// Independent electrons in a given monochromatic plane wave travelling along
+// +x (the single-particle tests of Section 3): A_y = a_y sin(phi + psi),
+// A_z = a_z cos(phi + psi), phi = t - x, E_perp = -dA/dphi, B = (0, -E_z, E_y).
+struct TrackArgs {
+  double ay, az, psi;
+  double dt, t0;
+  double eps;
+  long long steps, n;
+  double* x;
+  double* ux;
+  double* uy;
+  double* uz;
+};
+
+// Fields (and, for the complete force, their partial derivatives) at (x, t)
+template <typename R>
+__device__ __forceinline__ void wave_at(const TrackArgs& a, double x, double t, R& ey, R& ez,
+                                        FieldRates<R>& fr) {
+  double sn, cs;
+  sincos(t - x + a.psi, &sn, &cs);
+  ey = (R)(-a.ay * cs);
+  ez = (R)(a.az * sn);
+  // dE_perp/dphi = (a_y sin, a_z cos); d/dt = d/dphi, d/dx = -d/dphi
+  const R dy = (R)(a.ay * sn), dz = (R)(a.az * cs);
+  fr.etx = R(0);
+  fr.ety = dy;
+  fr.etz = dz;
+  fr.bty = -dz;
+  fr.btz = dy;
+  fr.exx = R(0);
+  fr.exy = -dy;
+  fr.exz = -dz;
+  fr.bxy = dz;
+  fr.bxz = -dy;
+}
+
+// The paper's leapfrog scheme: x^n and u^{n-1/2} in, x^{n+steps} and
+// u^{n+steps-1/2} out; the position advances in FP64 by dt u_x / gamma.
+// MODE: 0 Lorentz only, 1 with f_R of Eq. (f_r), 2 with the complete force.
+template <typename R, int MODE>
+__global__ void k_track_leapfrog(TrackArgs a) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  constexpr bool COMP = sizeof(R) == 4 && MODE > 0;
+  double x = a.x[i];
+  R ux = (R)a.ux[i], uy = (R)a.uy[i], uz = (R)a.uz[i];
+  float rx = 0.f, ry = 0.f, rz = 0.f, stiff = 0.f;
+  const R qh = (R)(-0.5 * a.dt), k = (R)(a.eps * a.dt);
+  for (long long s = 0; s < a.steps; ++s) {
+    R ey, ez;
+    FieldRates<R> fr;
+    wave_at<R>(a, x, a.t0 + (double)s * a.dt, ey, ez, fr);
+    MomentumOut<R> o;
+    momentum_step<R, (MODE > 0), COMP, (MODE == 2)>(ux, uy, uz, R(0), ey, ez, -ez, ey, qh, k, fr, rx,
+                                                    ry, rz, stiff, o);
+    ux = o.nx;
+    uy = o.ny;
+    uz = o.nz;
+    const double gx = (double)ux + rx, gy = (double)uy + ry, gz = (double)uz + rz;
+    x += a.dt * gx / sqrt(1.0 + gx * gx + gy * gy + gz * gz);
+  }
+  a.x[i] = x;
+  a.ux[i] = (double)ux + rx;
+  a.uy[i] = (double)uy + ry;
+  a.uz[i] = (double)uz + rz;
+}
+
+// Right-hand side of Eq. (3dLL) for an electron (MODE 0: Lorentz only; 1:
+// plus the non-derivative RR terms; 2: plus the derivative term).
+template <typename R, int MODE>
+__device__ __forceinline__ void ll_rhs(R ux, R uy, R uz, R ey, R ez, const FieldRates<R>& fr, R eps,
+                                       R& fx, R& fy, R& fz) {
+  const R by = -ez, bz = ey;
+  const R g2 = R(1) + ux * ux + uy * uy + uz * uz;
+  const R ig = R(1) / sqrt(g2);
+  const R vx = ux * ig, vy = uy * ig, vz = uz * ig;
+  const R Fx = vy * bz - vz * by, Fy = ey - vx * bz, Fz = ez + vx * by;  // E + v x B (E_x = 0)
+  fx = -Fx;
+  fy = -Fy;
+  fz = -Fz;
+  if (MODE > 0) {
+    const R vE = vy * ey + vz * ez;
+    const R br = g2 * (Fx * Fx + Fy * Fy + Fz * Fz - vE * vE);
+    fx += eps * ((Fy * bz - Fz * by) - br * vx);
+    fy += eps * (vE * ey - Fx * bz - br * vy);
+    fz += eps * (Fx * by + vE * ez - br * vz);
+  }
+  if (MODE == 2) {
+    const R g = g2 * ig;
+    const R DEy = fr.ety + vx * fr.exy, DEz = fr.etz + vx * fr.exz;
+    const R DBy = fr.bty + vx * fr.bxy, DBz = fr.btz + vx * fr.bxz;
+    fx -= eps * g * (vy * DBz - vz * DBy);
+    fy -= eps * g * (DEy - vx * DBz);
+    fz -= eps * g * (DEz + vx * DBy);
+  }
+}
+
+// Classical RK4 of (x, u) at the same time, the comparator of Section 3.
+template <typename R, int MODE>
+__global__ void k_track_rk4(TrackArgs a) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  double x = a.x[i];
+  R ux = (R)a.ux[i], uy = (R)a.uy[i], uz = (R)a.uz[i];
+  const R h = (R)a.dt, eps = (R)a.eps;
+  auto stage = [&](double xs, double ts, R sx, R sy, R sz, double& dx, R& fx, R& fy, R& fz) {
+    R ey, ez;
+    FieldRates<R> fr;
+    wave_at<R>(a, xs, ts, ey, ez, fr);
+    ll_rhs<R, MODE>(sx, sy, sz, ey, ez, fr, eps, fx, fy, fz);
+    dx = (double)sx / sqrt(1.0 + (double)sx * sx + (double)sy * sy + (double)sz * sz);
+  };
+  for (long long s = 0; s < a.steps; ++s) {
+    const double t = a.t0 + (double)s * a.dt;
+    double d1, d2, d3, d4;
+    R a1, b1, c1, a2, b2, c2, a3, b3, c3, a4, b4, c4;
+    stage(x, t, ux, uy, uz, d1, a1, b1, c1);
+    stage(x + 0.5 * a.dt * d1, t + 0.5 * a.dt, ux + R(0.5) * h * a1, uy + R(0.5) * h * b1,
+          uz + R(0.5) * h * c1, d2, a2, b2, c2);
+    stage(x + 0.5 * a.dt * d2, t + 0.5 * a.dt, ux + R(0.5) * h * a2, uy + R(0.5) * h * b2,
+          uz + R(0.5) * h * c2, d3, a3, b3, c3);
+    stage(x + a.dt * d3, t + a.dt, ux + h * a3, uy + h * b3, uz + h * c3, d4, a4, b4, c4);
+    x += a.dt / 6.0 * (d1 + 2.0 * d2 + 2.0 * d3 + d4);
+    ux += h / R(6) * (a1 + R(2) * a2 + R(2) * a3 + a4);
+    uy += h / R(6) * (b1 + R(2) * b2 + R(2) * b3 + b4);
+    uz += h / R(6) * (c1 + R(2) * c2 + R(2) * c3 + c4);
+  }
+  a.x[i] = x;
+  a.ux[i] = ux;
+  a.uy[i] = uy;
+  a.uz[i] = uz;
 }
 
 // ---------------------------------------------------------------- self-check

@@ -961,6 +961,56 @@ pic_status pic_spectrum(pic_run* r, int32_t bins, double e_max, double* host_his
   return PIC_OK;
 }
 
+pic_status pic_track(const pic_wave* wave, int32_t scheme, int32_t rr, int32_t precision,
+                     double lambda_um, double dt, double t0, int64_t steps, int64_t n, double* d_x,
+                     double* d_ux, double* d_uy, double* d_uz, void* stream) {
+  if (!wave) return fail(PIC_EINVAL, "null wave");
+  if (scheme != PIC_TRACK_LEAPFROG && scheme != PIC_TRACK_RK4) return fail(PIC_EINVAL, "unknown scheme");
+  if (rr != PIC_RR_OFF && rr != PIC_RR_REDUCED && rr != PIC_RR_FULL) return fail(PIC_EINVAL, "unknown rr mode");
+  if (precision != PIC_FP32 && precision != PIC_FP64) return fail(PIC_EINVAL, "bad precision");
+  if (!(lambda_um > 0.0) || !(dt > 0.0) || steps < 0 || n < 0 || !std::isfinite(t0))
+    return fail(PIC_EINVAL, "bad wavelength, step, count or start time");
+  if (!std::isfinite(wave->a_y) || !std::isfinite(wave->a_z) || !std::isfinite(wave->psi))
+    return fail(PIC_EINVAL, "non-finite wave parameters");
+  if (n > 0 && (!d_x || !d_ux || !d_uy || !d_uz)) return fail(PIC_EINVAL, "null particle arrays");
+  if (n == 0 || steps == 0) return PIC_OK;
+  TrackArgs a{};
+  a.ay = wave->a_y;
+  a.az = wave->a_z;
+  a.psi = wave->psi;
+  a.dt = dt;
+  a.t0 = t0;
+  a.eps = 4.0 * M_PI / 3.0 * kRe_um / lambda_um;
+  a.steps = steps;
+  a.n = n;
+  a.x = d_x;
+  a.ux = d_ux;
+  a.uy = d_uy;
+  a.uz = d_uz;
+  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  hipStream_t st = S(stream);
+  const bool f32 = precision == PIC_FP32;
+#define PIC_TRACK_LAUNCH(K, M)                                                      \
+  do {                                                                              \
+    if (f32)                                                                        \
+      hipLaunchKernelGGL((K<float, M>), grid, block, 0, st, a);                     \
+    else                                                                            \
+      hipLaunchKernelGGL((K<double, M>), grid, block, 0, st, a);                    \
+  } while (0)
+  if (scheme == PIC_TRACK_LEAPFROG) {
+    if (rr == PIC_RR_OFF) PIC_TRACK_LAUNCH(k_track_leapfrog, 0);
+    else if (rr == PIC_RR_REDUCED) PIC_TRACK_LAUNCH(k_track_leapfrog, 1);
+    else PIC_TRACK_LAUNCH(k_track_leapfrog, 2);
+  } else {
+    if (rr == PIC_RR_OFF) PIC_TRACK_LAUNCH(k_track_rk4, 0);
+    else if (rr == PIC_RR_REDUCED) PIC_TRACK_LAUNCH(k_track_rk4, 1);
+    else PIC_TRACK_LAUNCH(k_track_rk4, 2);
+  }
+#undef PIC_TRACK_LAUNCH
+  HIP_TRY(hipGetLastError());
+  return PIC_OK;
+}
+
 pic_status pic_check_rounding(uint32_t first, uint32_t count, unsigned long long* d_mismatches,
                               void* stream) {
   if (!d_mismatches) return fail(PIC_EINVAL, "null mismatch counter");

@@ -1,0 +1,133 @@
+"""Test electrons in a given plane wave on the GPU (pic_track), the
+single-particle tests of Section 3: against the oracle's pusher step by step
+(with and without the derivative term of Eq. (3dLL)), against the exact
+plane-wave orbits (reduced and complete force), the worked example, and the
+RK4 comparator."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import analytic, pusher, rk4
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+WAVE = dict(a_y=30.0, a_z=20.0, psi=0.4)
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    print(f"\n[gpu] {request.node.name}", flush=True)
+    yield
+    torch.cuda.synchronize()
+
+
+def _track(*a, **k):
+    from paper_1008_1685_amd.track import track
+
+    return track(*a, **k)
+
+
+@pytest.mark.parametrize("rr", ["off", "reduced", "full"])
+def test_one_leapfrog_step_matches_the_oracle(rr):
+    rng = np.random.default_rng(11)
+    n = 4096
+    wave = analytic.MonochromaticWave(300.0, 200.0, psi=0.3)
+    x = rng.uniform(-50, 50, n)
+    d = rng.normal(size=(n, 3))
+    u = d / np.linalg.norm(d, axis=1)[:, None] * np.exp(rng.uniform(np.log(1e-2), np.log(1e3), n))[:, None]
+    dt, t0, lam = 0.01, 3.7, 0.8
+    eps = pusher.rr_coefficient(lam)
+    xg, ug = _track(x, u, 300.0, 200.0, 0.3, dt=dt, steps=1, t0=t0, rr=rr, lambda_um=lam)
+    E, B = wave.fields(x, t0)
+    parts = wave.partials(x, t0) if rr == "full" else None
+    un, uL = pusher.push(u, E, B, -1.0, dt, eps, rr != "off", partials=parts)
+    nrm = lambda a: np.linalg.norm(a, axis=1)
+    scale = np.maximum.reduce([nrm(u), nrm(uL), nrm(un), dt * nrm(E), nrm(un - uL), np.full(n, 1e-2)])
+    assert np.max(np.linalg.norm(ug - un, axis=1) / scale) <= 1e-12
+    xn = x + dt * un[:, 0] / np.sqrt(1 + np.sum(un * un, 1))
+    dx = np.abs(xg - xn) / (1 + np.abs(x))
+    assert dx.max() <= 1e-12, (float(dx.max()), int(dx.argmax()))
+
+
+def _leapfrog_vs_exact(rr, dt, eps_scale=1.0, precision="fp64", t_end=12.0):
+    wave = analytic.MonochromaticWave(**{"a_y": WAVE["a_y"], "a_z": WAVE["a_z"], "psi": WAVE["psi"]})
+    u0 = np.array([-8.0, 2.0, -1.0])
+    lam = 0.8 / eps_scale  # eps = (4 pi / 3) r_e / lambda
+    eps = pusher.rr_coefficient(lam)
+    orb = analytic.PlaneWaveOrbit(wave, u0, eps=eps if rr != "off" else 0.0, phi_span=400.0,
+                                  full_ll=(rr == "full"))
+    _, uh, _ = orb.at_time(-0.5 * dt)
+    n = int(round(t_end / dt))
+    xg, ug = _track([0.0], [uh], **WAVE, dt=dt, steps=n, rr=rr, precision=precision, lambda_um=lam)
+    xa, ua, _ = orb.at_time(n * dt)
+    return xg[0], xa, orb
+
+
+def test_leapfrog_converges_to_the_complete_ll_orbit():
+    # strong (amplified) RR: the scheme is first order in the RR part
+    # (Eq. (estim1) leaves out the RR increment); weak RR: second order
+    e = [abs(x - xa) for x, xa, _ in (_leapfrog_vs_exact("full", dt, 2e3) for dt in (0.04, 0.02))]
+    assert 1.7 < e[0] / e[1] < 2.6
+    e = [abs(x - xa) for x, xa, _ in (_leapfrog_vs_exact("full", dt, 20.0) for dt in (0.02, 0.01))]
+    assert e[0] / e[1] == pytest.approx(4.0, rel=0.2)
+
+
+def test_gpu_sees_the_derivative_term_as_the_exact_solutions_do():
+    # amplified RR (x 2000) so that the derivative term is resolved
+    xr, xar, _ = _leapfrog_vs_exact("reduced", 0.005, 2e3)
+    xf, xaf, _ = _leapfrog_vs_exact("full", 0.005, 2e3)
+    exact = xaf - xar
+    assert abs(exact) > 5e-5
+    assert abs((xf - xr) - exact) <= 0.05 * abs(exact)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_worked_example(precision):
+    # Section 3: p_x0 = -200, a0 = 350, 0.8 um, dt = 0.01, 500/omega: the paper
+    # reports ~4e-4 relative error of the longitudinal displacement
+    g = json.load(open(os.path.join(GOLDEN, "worked_example.json")))
+    wave = analytic.MonochromaticWave(g["a0"])
+    eps = pusher.rr_coefficient(g["lambda_um"])
+    res = {}
+    for rr in ("reduced", "full"):
+        orb = analytic.PlaneWaveOrbit(wave, np.array([g["p_x0"], 0, 0]), eps=eps, phi_span=4000.0,
+                                      full_ll=(rr == "full"))
+        _, uh, _ = orb.at_time(-0.5 * g["dt"])
+        n = int(round(g["t_end"] / g["dt"]))
+        xg, ug = _track([0.0], [uh], g["a0"], dt=g["dt"], steps=n, rr=rr, precision=precision,
+                        lambda_um=g["lambda_um"])
+        xa, ua, _ = orb.at_time(n * g["dt"])
+        res[rr] = (xg[0], xa)
+        rel = abs(xg[0] - xa) / abs(xa)
+        print(f"[{precision} {rr}] x = {xg[0]:.9f}, exact {xa:.9f}, relative error {rel:.2e}", flush=True)
+        assert rel <= g["rel_displacement_error_reported"]
+        assert ug[0, 0] > 0  # RR turned the electron round
+    # the derivative term moves the orbit by ~2e-9 relative: negligible
+    (xr, xar), (xf, xaf) = res["reduced"], res["full"]
+    assert abs(xaf - xar) / abs(xar) < 1e-8
+
+
+def test_rk4_matches_the_oracle_comparator_and_converges_at_fourth_order():
+    wave = analytic.MonochromaticWave(**WAVE)
+    u0 = np.array([-8.0, 2.0, -1.0])
+    lam = 0.8 / 20.0
+    eps = pusher.rr_coefficient(lam)
+    t_end = 12.0
+    orb = analytic.PlaneWaveOrbit(wave, u0, eps=eps, phi_span=400.0, full_ll=True)
+    xa, ua, _ = orb.at_time(t_end)
+    errs = []
+    for dt in (0.02, 0.01):
+        n = int(round(t_end / dt))
+        xg, ug = _track([0.0], [u0], **WAVE, dt=dt, steps=n, scheme="rk4", rr="full", lambda_um=lam)
+        errs.append(np.linalg.norm(ug[0] - ua) / np.linalg.norm(ua))
+        if dt == 0.02:
+            xo, uo = rk4.track(wave, np.zeros(3), u0, 0.0, dt, n, eps, "full")
+            np.testing.assert_allclose(ug[0], uo, rtol=1e-11, atol=1e-11)
+            assert abs(xg[0] - xo[0]) <= 1e-11 * max(1.0, abs(xo[0]))
+    assert errs[0] / errs[1] == pytest.approx(16.0, rel=0.2)
