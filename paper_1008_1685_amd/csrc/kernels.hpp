@@ -112,6 +112,15 @@ struct PushArgs {
   R sw;                          // 256 / w_ref (charge-weight scale)
   int qw_ref[2];                 // charge weight of a particle of weight w_ref
   int ntiles;                    // tiles of both species
+  // Cell range of every tile after the previous push (the particles' cells
+  // now, as long as no sort or state change came between): with *pred_in
+  // set, a tile sizes its current window from it instead of a pass over its
+  // cells.  Only a hint: a particle outside the window deposits by global
+  // atomics.  The push writes the next ranges and sets *pred_out.
+  const int* rng_in;             // [tile][2] min, max
+  int* rng_out;
+  const int* pred_in;
+  int* pred_out;
 };
 
 // ---------------------------------------------------------------- helpers
@@ -320,9 +329,9 @@ __device__ __forceinline__ void deposit(DepositCtx& d, int c, R o, int c1, R o1,
   const int tz2 = (int)(((long long)vz24 * (wo2 + wn2)) >> 25);
   const bool moved = (c1 != c);
   const int j0 = base + 1;  // Jx half-node base+1/2 and Jy node base share index base+1
-  if (d.use_lds && qw == d.qw_ref) {
+  const int r = j0 - d.wlo;  // 0 <= r <= W - 3 when the particle's cell is in the window
+  if (d.use_lds && qw == d.qw_ref && (unsigned)r <= (unsigned)(d.W - 3)) {
     // LDS holds sums of unweighted terms; the flush multiplies by qw_ref
-    const int r = j0 - d.wlo;  // 0 <= r <= W - 3 by construction of the window
     // slot (comp, r + k) of this lane's copy: x0 + comp * cs + k * ss
     const int ss = d.P, cs = d.W * d.P;
     unsigned long long* x0 = d.lds + d.copy + r * d.P;
@@ -362,6 +371,7 @@ __device__ __forceinline__ void deposit(DepositCtx& d, int c, R o, int c1, R o1,
 // work-group sum on)
 struct PushAcc {
   float rad, esc, stiff;
+  int cmin1, cmax1;  // range of the new cells of the thread's particles
 };
 
 // Stored state of one particle (besides its cell).
@@ -561,6 +571,8 @@ __device__ __forceinline__ void push_particle(const PushArgs<R>& a, const Specie
   } else {
     st(sp.cell, ui, c1);
     st(sp.off, ui, o1);
+    acc.cmin1 = min(acc.cmin1, c1);
+    acc.cmax1 = max(acc.cmax1, c1);
   }
   st(sp.ux, ui, nx);
   st(sp.uy, ui, ny);
@@ -588,32 +600,46 @@ __device__ __forceinline__ void push_tile(const PushArgs<R>& a, int s, int tile,
 #pragma unroll
   for (int k = 0; k < D; ++k) ring[k] = load_particle<R, COMP>(sp, base + k * kThreads + tid, n);
 
-  // the tile's cell range (from the ring when it holds the whole tile)
+  // the tile's cell range: as the previous push left it, when that is
+  // known, else from a pass over the cells (from the ring when it holds the
+  // whole tile)
   int cmin = INT_MAX, cmax = INT_MIN;
+  if (__builtin_amdgcn_readfirstlane(*a.pred_in)) {
+    cmin = __builtin_amdgcn_readfirstlane(a.rng_in[2 * tile]);
+    cmax = __builtin_amdgcn_readfirstlane(a.rng_in[2 * tile + 1]);
+  } else {
 #pragma unroll
-  for (int k = 0; k < PPT; ++k) {
-    int c;
-    if constexpr (PPT == D) {
-      c = ring[k].c;
-    } else {
-      const int i = base + k * kThreads + tid;
-      c = i < n ? ld(sp.cell, (unsigned)i) : kDead;
+    for (int k = 0; k < PPT; ++k) {
+      int c;
+      if constexpr (PPT == D) {
+        c = ring[k].c;
+      } else {
+        const int i = base + k * kThreads + tid;
+        c = i < n ? ld(sp.cell, (unsigned)i) : kDead;
+      }
+      if (c != kDead) {
+        cmin = min(cmin, c);
+        cmax = max(cmax, c);
+      }
     }
-    if (c != kDead) {
-      cmin = min(cmin, c);
-      cmax = max(cmax, c);
+    cmin = wave_min_dpp(cmin);
+    cmax = wave_max_dpp(cmax);
+    if (lane == 0) {
+      s_mn[wid] = cmin;
+      s_mx[wid] = cmax;
     }
+    __syncthreads();
+    cmin = min(min(s_mn[0], s_mn[1]), min(s_mn[2], s_mn[3]));
+    cmax = max(max(s_mx[0], s_mx[1]), max(s_mx[2], s_mx[3]));
   }
-  cmin = wave_min_dpp(cmin);
-  cmax = wave_max_dpp(cmax);
-  if (lane == 0) {
-    s_mn[wid] = cmin;
-    s_mx[wid] = cmax;
+  if (cmin > cmax) {  // every particle of the tile was removed
+    if (tid == 0) {
+      a.rng_out[2 * tile] = INT_MAX;
+      a.rng_out[2 * tile + 1] = INT_MIN;
+      *a.pred_out = 1;
+    }
+    return;
   }
-  __syncthreads();
-  cmin = min(min(s_mn[0], s_mn[1]), min(s_mn[2], s_mn[3]));
-  cmax = max(max(s_mx[0], s_mx[1]), max(s_mx[2], s_mx[3]));
-  if (cmin > cmax) return;  // every particle of the tile was removed
 
   // window: storage indices cmin .. cmax + 3 (nodes cmin - 1 .. cmax + 2),
   // with as many private copies per slot (up to 64) as the LDS holds
@@ -635,7 +661,7 @@ __device__ __forceinline__ void push_tile(const PushArgs<R>& a, int s, int tile,
     for (int e = tid; e < E; e += kThreads) lds[e] = 0ull;
   __syncthreads();
 
-  PushAcc acc{0.f, 0.f, 0.f};
+  PushAcc acc{0.f, 0.f, 0.f, INT_MAX, INT_MIN};
   // ring slot j holds particle k0 + j; its successor D ahead is loaded
   // before particle k0 + j is computed
 #pragma unroll kRingUnroll
@@ -651,10 +677,13 @@ __device__ __forceinline__ void push_tile(const PushArgs<R>& a, int s, int tile,
 
   const double r0 = wave_sum_dpp((double)acc.rad), r1 = wave_sum_dpp((double)acc.esc),
                r2 = wave_sum_dpp((double)acc.stiff);
+  const int n0 = wave_min_dpp(acc.cmin1), n1 = wave_max_dpp(acc.cmax1);
   if (lane == 0) {
     s_red[0][wid] = r0;
     s_red[1][wid] = r1;
     s_red[2][wid] = r2;
+    s_mn[wid] = n0;
+    s_mx[wid] = n1;
   }
   __syncthreads();
 
@@ -685,6 +714,10 @@ __device__ __forceinline__ void push_tile(const PushArgs<R>& a, int s, int tile,
       t1 += s_red[1][w];
       t2 += s_red[2][w];
     }
+    // the tile's cells for the next push
+    a.rng_out[2 * tile] = min(min(s_mn[0], s_mn[1]), min(s_mn[2], s_mn[3]));
+    a.rng_out[2 * tile + 1] = max(max(s_mx[0], s_mx[1]), max(s_mx[2], s_mx[3]));
+    *a.pred_out = 1;
     // one add per slot and launch, in launch order: deterministic; the
     // atomic form needs no load, so the work-group retires without waiting
     double* A = a.acc + 4 * (size_t)tile;
@@ -913,6 +946,7 @@ struct SortArgs {
   int blocks0;          // blocks of species 0 in hist / scatter grids
   int nx;
   int comp;             // carry residuals of species 0
+  int* pred;            // [2] the push's range-prediction flags, cleared: the order changes
 };
 
 constexpr int kSortThreads = 256;
@@ -1085,6 +1119,7 @@ __device__ __forceinline__ void sort_scatter_block(const SortArgs<R>& p, int blk
   const int b = s ? blk - p.blocks0 : blk;
   const long long n = p.count[s];
   const long long base = (long long)b * kSortTile;
+  if (blk == 0 && threadIdx.x == 0) p.pred[0] = p.pred[1] = 0;
   if (base >= n) return;
   const SpeciesDev<R> src = p.src[s], dst = p.dst[s];
   const bool comp = s == 0 && p.comp;

@@ -134,6 +134,8 @@ struct pic_run {
   long long* step_dev;
   int* flags;
   double* acc;          // [tiles][4]
+  int* trange;          // [2 parities][tiles][2]: tile cell ranges left by the push
+  int* tpred;           // [2 parities]: the ranges of that parity match the particles
   double* budget;       // [4]
   int* cnt[2];
   int* cursor[2];
@@ -189,6 +191,8 @@ void carve(pic_run* r, Carver& cv) {
   r->flags = cv.take<int>(4);
   r->tiles_max = 2 * tiles_for(d.cap, kMinTile);  // a run may also step in a batch
   r->acc = cv.take<double>(4 * (size_t)std::max(r->tiles_max, 1));
+  r->trange = cv.take<int>(4 * (size_t)std::max(r->tiles_max, 1));
+  r->tpred = cv.take<int>(2);
   r->budget = cv.take<double>(4);
   for (int s = 0; s < 2; ++s) {
     r->cnt[s] = cv.take<int>(d.nx + 1);
@@ -295,6 +299,11 @@ PushArgs<R> make_push_args(const pic_run* r, int pp, int fp, int tile = kTile) {
   for (int s = 0; s < 2; ++s)  // the kernel's own rounding of a particle of weight w_ref
     a.qw_ref[s] = a.Z[s] * (int)std::rint((R)d.w_ref * a.sw);
   a.ntiles = a.tiles0 + tiles_for(r->n_max[1], tile);
+  const size_t rt = 2 * (size_t)std::max(r->tiles_max, 1);
+  a.rng_in = r->trange + fp * rt;
+  a.rng_out = r->trange + (fp ^ 1) * rt;
+  a.pred_in = r->tpred + fp;
+  a.pred_out = r->tpred + (fp ^ 1);
   return a;
 }
 
@@ -344,6 +353,7 @@ SortArgs<R> make_sort_args(const pic_run* r, int pp) {
   p.nx = r->d.nx;
   p.comp = comp_on(r) ? 1 : 0;
   p.blocks0 = sort_blocks_for(r->n_max[0]);
+  p.pred = r->tpred;
   return p;
 }
 
@@ -857,6 +867,7 @@ pic_status pic_set_state(pic_run* r, const pic_state* st, void* stream) {
   const Derived& d = r->d;
   const size_t rs = rsz(r);
   HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipMemset(r->tpred, 0, 2 * sizeof(int)));  // the tile ranges no longer hold
   if (st->step >= 0 && st->step != r->step) {
     // move the fields to the buffer parity of the new step
     const int po = (int)(r->step & 1), pn = (int)(st->step & 1);
@@ -1123,6 +1134,8 @@ pic_status pic_batch_admit(pic_batch* b, pic_run* r, int64_t n_steps, void* stre
   b->target[free_slot] = n_steps;
   for (int k = 0; k < 3; ++k) b->nblk[k][free_slot] = need[k];
   hipStream_t st = S(stream);
+  // batched steps use their own tile size: the push's tile ranges restart
+  HIP_TRY(hipMemsetAsync(r->tpred, 0, 2 * sizeof(int), st));
   pic_status ps = b->prec == PIC_FP32 ? write_slot<float>(b, free_slot, st) : write_slot<double>(b, free_slot, st);
   if (!ps) ps = write_ranges(b, st);
   if (ps) {
@@ -1172,6 +1185,7 @@ pic_status pic_batch_release(pic_batch* b, int32_t slot, void* stream) {
   // sorts ran at the starts of steps K, 2K, ... below `step`
   r->pp = step > 0 ? (int)(((step - 1) / r->cfg.sort_interval) & 1) : 0;
   r->batch = nullptr;
+  HIP_TRY(hipMemsetAsync(r->tpred, 0, 2 * sizeof(int), st));  // single-run tiles from here
   b->runs[slot] = nullptr;
   b->target[slot] = 0;
   for (int k = 0; k < 3; ++k) b->nblk[k][slot] = 0;
