@@ -142,9 +142,15 @@ __device__ __forceinline__ T ld(const T* p, unsigned i) {
   return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) +
                                      (size_t)(i * (unsigned)sizeof(T)));
 }
+// The empty asm re-creates the 32-bit offset in the store's own basic block:
+// instruction selection works per block and matches the scalar-base form
+// only when it sees the zero extension of the offset, which after the
+// push's branches it otherwise does not (a 64-bit add per store).
 template <typename T>
 __device__ __forceinline__ void st(T* p, unsigned i, T v) {
-  *reinterpret_cast<T*>(reinterpret_cast<char*>(p) + (size_t)(i * (unsigned)sizeof(T))) = v;
+  unsigned o = i * (unsigned)sizeof(T);
+  asm volatile("" : "+v"(o));
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(p) + (size_t)o) = v;
 }
 
 __device__ __forceinline__ long long wave_sum(long long v) {
