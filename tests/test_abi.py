@@ -65,3 +65,32 @@ def test_null_arguments_are_rejected_without_a_gpu():
     from paper_1008_1685_amd.run import make_config
     c = make_config(preset("c1"))
     assert lib.pic_init(C.byref(c), None, 0, None, C.byref(h)) == N.PIC_EINVAL
+
+
+def test_track_and_particle_reads_validate_on_the_host():
+    lib = N.load()
+    w = N.PicWave(10.0, 0.0, 0.0)
+    x = (C.c_double * 4)()
+    args = lambda **k: dict(dict(wave=C.byref(w), scheme=0, rr=1, prec=N.PIC_FP64, lam=0.8, dt=0.01,
+                                 t0=0.0, steps=10, n=4, p=C.cast(x, C.c_void_p)), **k)
+
+    def call(a):
+        return lib.pic_track(a["wave"], a["scheme"], a["rr"], a["prec"], a["lam"], a["dt"], a["t0"],
+                             a["steps"], a["n"], a["p"], a["p"], a["p"], a["p"], None)
+
+    assert call(args(wave=None)) == N.PIC_EINVAL
+    assert call(args(scheme=7)) == N.PIC_EINVAL
+    assert call(args(rr=3)) == N.PIC_EINVAL
+    assert call(args(prec=5)) == N.PIC_EINVAL
+    assert call(args(dt=0.0)) == N.PIC_EINVAL
+    assert call(args(lam=-1.0)) == N.PIC_EINVAL
+    assert call(args(steps=-1)) == N.PIC_EINVAL
+    assert call(args(p=None)) == N.PIC_EINVAL
+    assert call(args(t0=float("nan"))) == N.PIC_EINVAL
+    w.a_y = float("inf")
+    assert call(args()) == N.PIC_EINVAL
+    # nothing to do: no launch, no device needed
+    w.a_y = 10.0
+    assert call(args(n=0, p=None)) == N.PIC_OK
+    sp = N.PicSpeciesState()
+    assert lib.pic_get_particles(None, 0, 0, 1, C.byref(sp), None) == N.PIC_EINVAL
