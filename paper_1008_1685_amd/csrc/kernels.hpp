@@ -1410,18 +1410,20 @@ __device__ __forceinline__ SlotRanges load_ranges(const int* start, int n, int* 
 template <typename R>
 __global__ PIC_PUSH_BOUNDS void k_push_batch(const SlotDev<R>* __restrict__ slots, const int* __restrict__ start, int n) {
   __shared__ unsigned long long lds[kLdsSlots];
-  // the slot ranges are read before the tile's first barrier and the deposit
-  // window is cleared only after it, so the two share the LDS
+  // the slot table and the deposit window share the LDS: every wave reads
+  // the table before the barrier below, the window is cleared after it
   static_assert((kMaxSlots + 1) * sizeof(int) <= sizeof(lds), "slot ranges must fit the window");
   const SlotRanges sr = load_ranges(start, n, reinterpret_cast<int*>(lds));
   const int b = (int)blockIdx.x;
-  if (b >= sr.total()) return;
+  if (b >= sr.total()) return;  // block-uniform, as are the returns below
   const int sl = sr.slot(b);
+  const int tile = b - sr.first(sl);
+  __syncthreads();
   const SlotDev<R>& S = slots[sl];
   const long long st = uniform(*S.step);
   if (st >= S.target) return;
   const int pp = (int)((st / S.sort_interval) & 1), fp = (int)(st & 1);
-  push_one_tile<R, kBatchPPT, kBatchPPT>(S.push[pp][fp], b - sr.first(sl), lds);
+  push_one_tile<R, kBatchPPT, kBatchPPT>(S.push[pp][fp], tile, lds);
 }
 
 template <typename R>

@@ -89,3 +89,22 @@ def test_budget_and_slot_reuse():
         assert r["diag"]["gauss_int"] == 0
         assert r["diag"]["step"] == r["steps"]
         assert r["latency"] >= r["done"] - r["admitted"] >= 0
+
+
+def test_every_run_of_a_request_stream_conserves_charge():
+    # many uneven runs sharing the batch through admission, sorts and slot
+    # reuse: each run's integer Gauss law must hold exactly at the end
+    from paper_1008_1685_amd.serve import Server
+    from workloads import poisson_stream
+
+    reqs = poisson_stream(0, n_runs=48, rate=20.0)
+    max_p = max(2 * r["cfg"]["ppc"] * round(r["cfg"]["thickness"] * r["cfg"]["cells_per_lambda"])
+                for r in reqs)
+    max_c = max(round(r["cfg"]["box_lambda"] * r["cfg"]["cells_per_lambda"]) for r in reqs)
+    srv = Server(budget_bytes=16 * 2 ** 30, max_slots=64, max_particles=64 * max_p,
+                 max_cells=64 * (max_c + 8))
+    recs = srv.serve(reqs)
+    assert len(recs) == len(reqs)
+    bad = [(r["name"], r["diag"]["gauss_int"], r["diag"]["nonfinite"]) for r in recs
+           if r["diag"]["gauss_int"] != 0 or r["diag"]["nonfinite"]]
+    assert not bad, bad
