@@ -81,6 +81,24 @@ def time_run(cfg, steps, warmup, diag_every, timing=TIMING_PERIOD):
     return out
 
 
+def side_by_side_c2(warmup=3200, steps=2000):
+    """The plain method at scale (12,000 cells, 4e5 particles, LP a0 = 300):
+    FP32 and FP64, RR on and off, each timed over the same window at the
+    start of the laser-foil interaction."""
+    out = {}
+    from workloads import preset
+
+    for prec in ("fp64", "fp32"):
+        for rr in (True, False):
+            cfg = preset("c2", precision=prec, rr=rr)
+            r = time_run(cfg, steps, warmup, steps, timing=0)
+            out[f"{prec}_rr_{'on' if rr else 'off'}"] = (r["n_e"] + r["n_i"]) * steps / r["seconds"]
+    out["speedup_fp32_over_fp64"] = out["fp32_rr_on"] / out["fp64_rr_on"]
+    out["rr_overhead_fp64"] = out["fp64_rr_off"] / out["fp64_rr_on"] - 1.0
+    out["workload"] = "c2: LP a0=300, 12000 cells, 400000 particles, steps 3200-5200, pushes/s"
+    return out
+
+
 def cpu_baseline(cfg, budget_s=20.0, max_steps=8):
     """The FP64 oracle, as is, on a bounded sample of the same workload."""
     from oracle import pic as opic
@@ -306,6 +324,7 @@ def main():
         line["rr_cost"] = dict(pushes_per_s_rr_off=v_off, overhead=v_off / value - 1.0,
                                paper="about +10% compute time with RR (Section 3)")
         line["fp64_path"] = dict(pushes_per_s=v_64, speedup_fp32_over_fp64=value / v_64)
+        line["plain_method_scale"] = side_by_side_c2()
         line["cpu_baseline"] = cpu_baseline(cfg)
     if not args.no_serve:
         line["serving"] = serve_bench()
