@@ -23,10 +23,15 @@ on Radiation Pressure Acceleration"):
 * ``pic``      - a plain 1D3V PIC loop (laser-foil problem of Section 4)
                  with Yee fields, linear weighting and charge-conserving
                  current deposition.
+* ``pic2d``    - the same loop on a 2D grid (2D3V, Section 4's remark that
+                 the pusher serves a multi-dimensional code unchanged):
+                 2D Yee fields, bilinear weighting, Esirkepov's 2D
+                 charge-conserving current.
+* ``contract2d`` - the fixed-point deposition contract of the 2D path.
 * ``rng``      - SplitMix64 counter-based generator for the quiet start.
 * ``spectrum`` - ion energy spectrum, its peak and its full width at half
                  maximum.
 
 Parity status per function is stated in each module header.
 """
-from . import pusher, analytic, contract, pic, rng, spectrum  # noqa: F401
+from . import pusher, analytic, contract, contract2d, pic, pic2d, rng, spectrum  # noqa: F401

@@ -78,3 +78,55 @@ def preset(name: str, **overrides) -> dict:
 def periods_to_steps(cfg: dict) -> int:
     """Steps in ``cfg['periods']`` laser periods: dt = cfl*dx, dx = lambda/cpl."""
     return int(round(cfg["periods"] * cfg["cells_per_lambda"] / cfg["cfl"]))
+
+
+# ---------------------------------------------------------------- 2D3V
+# The same laser-foil problem on a 2D grid, periodic in y: box_x by box_y
+# wavelengths, ppc_x * ppc_y particles per cell per species on a lattice,
+# laser with a Gaussian transverse profile of 1/e half-width ``waist``
+# wavelengths (0: plane wave).
+_BASE_2D = dict(
+    precision="fp32",
+    lambda_um=0.8,
+    cells_per_lambda=32,
+    box_x=10.0, box_y=2.0,
+    cfl=0.5,
+    pol="LP",
+    a0=100.0,
+    waist=0.6,
+    t_rise=3.0, t_flat=0.0, t_fall=3.0,
+    n0=90.0,
+    x_foil=4.0,
+    thickness=1.0,
+    ppc_x=2, ppc_y=2,
+    mass_ratio=1836.0,
+    rr=True,
+    rr_compensated=True,
+    seed=0,
+    jitter=0.5,
+    periods=8.0,
+    sort_interval=16,
+)
+
+PRESETS_2D = {
+    # small run that the FP64 oracle finishes: 320 x 64 cells, 16,384 particles
+    "d1": dict(_BASE_2D),
+    # the 2D counterpart of the precision-form workload: 2,560 x 1,024 cells,
+    # 8.4e6 particles (64 per cell per species), LP a0=500, 4-wavelength waist
+    "d2": dict(_BASE_2D, cells_per_lambda=64, box_x=40.0, box_y=16.0, a0=500.0, waist=4.0,
+               t_rise=5.0, t_fall=5.0, n0=100.0, x_foil=10.0, ppc_x=8, ppc_y=8,
+               periods=20.0),
+}
+
+
+def preset2d(name: str, **overrides) -> dict:
+    """Return a copy of 2D preset ``name`` with ``overrides`` applied."""
+    if name not in PRESETS_2D:
+        raise KeyError(f"unknown 2D preset {name!r}; known: {sorted(PRESETS_2D)}")
+    cfg = copy.deepcopy(PRESETS_2D[name])
+    for k, v in overrides.items():
+        if k not in cfg:
+            raise KeyError(f"unknown parameter {k!r}")
+        cfg[k] = v
+    cfg["name"] = name
+    return cfg
