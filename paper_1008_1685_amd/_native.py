@@ -1,4 +1,5 @@
-"""ctypes declarations of the C ABI in include/pic.h (argument marshalling only).
+"""ctypes declarations of the C ABI in include/pic.h and include/pic2d.h
+(argument marshalling only).
 
 The shared library is built in-tree as ``paper_1008_1685_amd/libpic.so``; a
 missing library is an error, there is no fallback path.
@@ -125,6 +126,88 @@ class PicState(C.Structure):
     ]
 
 
+class Pic2dConfig(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32),
+        ("precision", C.c_int32),
+        ("lambda_um", C.c_double),
+        ("cells_per_lambda", C.c_int32),
+        ("ppc_x", C.c_int32),
+        ("ppc_y", C.c_int32),
+        ("pol", C.c_int32),
+        ("box_x", C.c_double),
+        ("box_y", C.c_double),
+        ("cfl", C.c_double),
+        ("rr", C.c_int32),
+        ("rr_compensated", C.c_int32),
+        ("a0", C.c_double),
+        ("waist", C.c_double),
+        ("t_rise", C.c_double),
+        ("t_flat", C.c_double),
+        ("t_fall", C.c_double),
+        ("n0", C.c_double),
+        ("x_foil", C.c_double),
+        ("thickness", C.c_double),
+        ("mass_ratio", C.c_double),
+        ("sort_interval", C.c_int32),
+        ("reserved", C.c_int32),
+        ("seed", C.c_uint64),
+        ("jitter", C.c_double),
+        ("capacity", C.c_int64),
+    ]
+
+
+class Pic2dInfo(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32),
+        ("ny", C.c_int32),
+        ("y_shift", C.c_int32),
+        ("precision", C.c_int32),
+        ("dx", C.c_double),
+        ("dt", C.c_double),
+        ("eps_rr", C.c_double),
+        ("w_ref", C.c_double),
+        ("capacity", C.c_int64),
+        ("n_init", C.c_int64 * 2),
+        ("step", C.c_int64),
+        ("tile", C.c_int32),
+        ("lds_slots", C.c_int32),
+    ]
+
+
+class Pic2dSpeciesState(C.Structure):
+    _fields_ = [
+        ("count", C.c_int64),
+        ("cell", C.c_void_p),
+        ("ox", C.c_void_p),
+        ("oy", C.c_void_p),
+        ("ux", C.c_void_p),
+        ("uy", C.c_void_p),
+        ("uz", C.c_void_p),
+        ("w", C.c_void_p),
+        ("rx", C.c_void_p),
+        ("ry", C.c_void_p),
+        ("rz", C.c_void_p),
+    ]
+
+
+class Pic2dState(C.Structure):
+    _fields_ = [
+        ("sp", Pic2dSpeciesState * 2),
+        ("Ex", C.c_void_p),
+        ("Ey", C.c_void_p),
+        ("Ez", C.c_void_p),
+        ("Bx", C.c_void_p),
+        ("By", C.c_void_p),
+        ("Bz", C.c_void_p),
+        ("Jx_int", C.c_void_p),
+        ("Jy_int", C.c_void_p),
+        ("Jz_int", C.c_void_p),
+        ("charge_int", C.c_void_p),
+        ("step", C.c_int64),
+    ]
+
+
 # exported symbols: name -> (restype, argtypes)
 SIGNATURES = {
     "pic_workspace_bytes": (C.c_int, [C.POINTER(PicConfig), C.POINTER(C.c_size_t)]),
@@ -160,6 +243,21 @@ SIGNATURES = {
     "pic_batch_poll": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.c_void_p]),
     "pic_batch_release": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     "pic_batch_free": (None, [C.c_void_p]),
+    "pic2d_workspace_bytes": (C.c_int, [C.POINTER(Pic2dConfig), C.POINTER(C.c_size_t)]),
+    "pic2d_init": (C.c_int, [C.POINTER(Pic2dConfig), C.c_void_p, C.c_size_t, C.c_void_p,
+                             C.POINTER(C.c_void_p)]),
+    "pic2d_step": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p]),
+    "pic2d_push_deposit": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "pic2d_field_advance": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "pic2d_sort": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "pic2d_diag": (C.c_int, [C.c_void_p, C.POINTER(PicDiagOut), C.c_void_p]),
+    "pic2d_get_info": (C.c_int, [C.c_void_p, C.POINTER(Pic2dInfo)]),
+    "pic2d_free": (None, [C.c_void_p]),
+    "pic2d_get_state": (C.c_int, [C.c_void_p, C.POINTER(Pic2dState), C.c_void_p]),
+    "pic2d_set_state": (C.c_int, [C.c_void_p, C.POINTER(Pic2dState), C.c_void_p]),
+    "pic2d_timing_enable": (C.c_int, [C.c_void_p, C.c_int32]),
+    "pic2d_timing_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                    C.c_void_p]),
 }
 
 _lib = None

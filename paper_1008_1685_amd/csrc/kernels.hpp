@@ -71,6 +71,7 @@ struct SpeciesDev {
   float* rx;  // compensated RR residuals (fp32 electrons), else null
   float* ry;
   float* rz;
+  R* oy;      // y offsets on a 2D grid, else null
 };
 
 // Grid fields, interleaved so that one particle gathers with four loads:
@@ -410,24 +411,43 @@ struct MomentumOut {
 // (estimgamma), added as in Eq. (pertfull).  qh = q dt / (2 m), k = eps dt.
 // COMP adds the increment by TwoSum and carries the FP32 rounding residual
 // in (rx, ry, rz).  DERIV adds the derivative term of Eq. (3dLL) at the same
-// p^(n) (the complete LL force, for tracking in given fields).
-template <typename R, bool RR, bool COMP, bool DERIV>
+// p^(n) (the complete LL force, for tracking in given fields).  BX takes a
+// non-zero B_x (multi-dimensional grids); without it B_x = 0, as in 1D, and
+// none of its terms is evaluated.
+template <typename R, bool RR, bool COMP, bool DERIV, bool BX = false>
 __device__ __forceinline__ void momentum_step(R ux, R uy, R uz, R ex, R ey, R ez, R by, R bz, R qh,
                                               R k, const FieldRates<R>& fr, float& rx, float& ry,
-                                              float& rz, float& stiff, MomentumOut<R>& o) {
-  // Boris (B_x = 0 in 1D)
+                                              float& rz, float& stiff, MomentumOut<R>& o,
+                                              R bx = R(0)) {
+  // Boris
   const R hx = qh * ex, hy = qh * ey, hz = qh * ez;
   const R mx = ux + hx, my = uy + hy, mz = uz + hz;
   const R igm = rsq(R(1) + mx * mx + my * my + mz * mz);
   const R ty = qh * by * igm, tz = qh * bz * igm;
-  const R sf = R(2) * rcp(R(1) + ty * ty + tz * tz);
-  const R px = mx + (my * tz - mz * ty);
-  const R py = my - mx * tz;
-  const R pz = mz + mx * ty;
+  R tx = R(0), den;
+  if constexpr (BX) {
+    tx = qh * bx * igm;
+    den = R(1) + tx * tx + ty * ty + tz * tz;
+  } else {
+    den = R(1) + ty * ty + tz * tz;
+  }
+  const R sf = R(2) * rcp(den);
+  R px = mx + (my * tz - mz * ty);
+  R py = my - mx * tz;
+  R pz = mz + mx * ty;
+  if constexpr (BX) {
+    py += mz * tx;
+    pz -= my * tx;
+  }
   const R sy = sf * ty, sz = sf * tz;
-  const R Lx = mx + (py * sz - pz * sy) + hx;
-  const R Ly = my - px * sz + hy;
-  const R Lz = mz + px * sy + hz;
+  R Lx = mx + (py * sz - pz * sy) + hx;
+  R Ly = my - px * sz + hy;
+  R Lz = mz + px * sy + hz;
+  if constexpr (BX) {
+    const R sx = sf * tx;
+    Ly += pz * sx;
+    Lz -= py * sx;
+  }
 
   R nx = Lx, ny = Ly, nz = Lz;
   R gL = R(0), ddx = R(0), ddy = R(0), ddz = R(0);
@@ -439,16 +459,26 @@ __device__ __forceinline__ void momentum_step(R ux, R uy, R uz, R ex, R ey, R ez
     const R vx = qx * ig, vy = qy * ig, vz = qz * ig;
     // F = E + v x B = -f_L
     const R Fx = ex + (vy * bz - vz * by);
-    const R Fy = ey - vx * bz;
-    const R Fz = ez + vx * by;
+    R Fy = ey - vx * bz;
+    R Fz = ez + vx * by;
+    if constexpr (BX) {
+      Fy += vz * bx;
+      Fz -= vy * bx;
+    }
     const R vE = vx * ex + vy * ey + vz * ez;
     R br = Fx * Fx + Fy * Fy + Fz * Fz - vE * vE;
     br = br > R(0) ? br : R(0);
     const R g2b = g2 * br;
     // dt f_R = dt eps [F x B + (v.E) E - gamma^2 (F^2 - (v.E)^2) v]
-    ddx = k * ((Fy * bz - Fz * by) + vE * ex - g2b * vx);
-    ddy = k * (vE * ey - Fx * bz - g2b * vy);
-    ddz = k * (Fx * by + vE * ez - g2b * vz);
+    if constexpr (BX) {
+      ddx = k * ((Fy * bz - Fz * by) + vE * ex - g2b * vx);
+      ddy = k * ((Fz * bx - Fx * bz) + vE * ey - g2b * vy);
+      ddz = k * ((Fx * by - Fy * bx) + vE * ez - g2b * vz);
+    } else {
+      ddx = k * ((Fy * bz - Fz * by) + vE * ex - g2b * vx);
+      ddy = k * (vE * ey - Fx * bz - g2b * vy);
+      ddz = k * (Fx * by + vE * ez - g2b * vz);
+    }
     if (DERIV) {
       // derivative term of Eq. (3dLL): -eps gamma [D E + v x D B], D = d/dt + v_x d/dx
       const R g = g2 * ig;
@@ -1116,8 +1146,9 @@ __global__ __launch_bounds__(1024) void k_sort_scan(int* cnt0, int* cnt1, int* c
 
 // scatter to the destination arrays: each tile claims, per occupied cell,
 // one contiguous range of the cell's bucket with a single global atomic and
-// hands out positions inside it through an LDS counter
-template <typename R>
+// hands out positions inside it through an LDS counter (OY: particles of a
+// 2D grid also carry a y offset)
+template <typename R, bool OY = false>
 __device__ __forceinline__ void sort_scatter_block(const SortArgs<R>& p, int blk) {
   __shared__ int cnt[kSortWin];
   __shared__ int sm[8];
@@ -1132,7 +1163,7 @@ __device__ __forceinline__ void sort_scatter_block(const SortArgs<R>& p, int blk
   int cl[kSortPPT], pos[kSortPPT];
   // the particles' data is loaded with their cells, so that its latency
   // overlaps the position claims below
-  R off[kSortPPT], ux[kSortPPT], uy[kSortPPT], uz[kSortPPT], w[kSortPPT];
+  R off[kSortPPT], ux[kSortPPT], uy[kSortPPT], uz[kSortPPT], w[kSortPPT], oy[kSortPPT];
   float rx[kSortPPT], ry[kSortPPT], rz[kSortPPT];
 #pragma unroll
   for (int k = 0; k < kSortPPT; ++k) {
@@ -1146,6 +1177,7 @@ __device__ __forceinline__ void sort_scatter_block(const SortArgs<R>& p, int blk
       uy[k] = ld(src.uy, ui);
       uz[k] = ld(src.uz, ui);
       w[k] = ld(src.w, ui);
+      if constexpr (OY) oy[k] = ld(src.oy, ui);
       if (comp) {
         rx[k] = ld(src.rx, ui);
         ry[k] = ld(src.ry, ui);
@@ -1183,6 +1215,7 @@ __device__ __forceinline__ void sort_scatter_block(const SortArgs<R>& p, int blk
     st(dst.uy, j, uy[k]);
     st(dst.uz, j, uz[k]);
     st(dst.w, j, w[k]);
+    if constexpr (OY) st(dst.oy, j, oy[k]);
     if (comp) {
       st(dst.rx, j, rx[k]);
       st(dst.ry, j, ry[k]);

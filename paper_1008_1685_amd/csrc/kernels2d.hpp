@@ -1,0 +1,864 @@
+// Device code of the 2D3V path (gfx950): the momentum step of the 1D3V
+// kernels (Boris plus the RR step of Section 3) on a 2D Yee grid, periodic
+// in y.  Section 4 notes that the 1D code's momentum space is already three
+// dimensional, so a multi-dimensional code uses the same pusher; here it is
+// the same device function, with B_x switched on.
+//
+// Kernels:
+//   k_push2     gather -> Boris -> RR (electrons) -> 2D move -> fixed-point
+//               Esirkepov deposit, one thread per particle over cell-sorted
+//               tiles.  A particle's 40 current terms (its old cell's 4 x 4
+//               node stencil) are summed over the lanes of each 16-lane row
+//               that share the old cell (DPP row shifts); the row's last
+//               lane adds the sums to an LDS box of the tile's cells, which
+//               goes to HBM with one 64-bit atomic per node at the end.
+//   k_field2_b  half step of B (run before and after the E step).
+//   k_field2_e  E step, boundary guards, Poynting bookkeeping, the running
+//               integer charge implied by the current, and the clearing of
+//               the next step's current.
+//   k_init2, k_diag2_*: quiet start and FP64 diagnostics.
+// The cell sort reuses the 1D kernels (the y offset moves with the particle).
+//
+// Cell key of a particle: ix << ysh | iy (ysh = bits of ny rounded up to a
+// power of two), so that (ix, iy) decode with a shift and a mask and the
+// counting sort orders particles column by column, rows fastest.  Grid
+// arrays are y-fastest with stride ny: component at (column X, row j) is
+// element X * ny + j.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace pic {
+
+#ifndef PIC2D_PUSH_PPT
+#define PIC2D_PUSH_PPT 8
+#endif
+#ifndef PIC2D_LDS_SLOTS
+#define PIC2D_LDS_SLOTS 4096
+#endif
+
+constexpr int k2Q = 12;                   // fixed-point bits of a shape weight
+constexpr int k2One = 1 << k2Q;
+constexpr int k2PPT = PIC2D_PUSH_PPT;     // particles per thread per tile
+constexpr int k2Tile = kThreads * k2PPT;
+constexpr int k2Slots = PIC2D_LDS_SLOTS;  // 64-bit LDS accumulators per work-group
+constexpr int k2Cols = 8;                 // columns of the LDS box (x)
+constexpr int k2MaxRows = k2Slots / (3 * k2Cols);
+constexpr int k2Terms = 40;               // 12 Jx + 12 Jy + 16 Jz terms per particle
+
+// staggered field pairs: (E_y, B_x) at (node, half-row), (E_x, B_y) at (half-node, row)
+template <typename R>
+struct alignas(2 * sizeof(R)) NH {
+  R ey, bx;
+};
+template <typename R>
+struct alignas(2 * sizeof(R)) HN {
+  R ex, by;
+};
+
+template <typename R>
+struct Fields2Dev {
+  R* ez;       // [(nx + 1) ny]  node, row
+  NH<R>* nh;   // [(nx + 1) ny]  node, half-row
+  HN<R>* hn;   // [(nx + 2) ny]  half-node, row
+  R* bz;       // [(nx + 2) ny]  half-node, half-row
+};
+
+// write one member of an interleaved pair without touching the other (a
+// neighbouring thread may be reading it)
+template <typename R, typename P>
+__device__ __forceinline__ void st_member(P* base, size_t i, int m, R v) {
+  reinterpret_cast<R*>(base)[2 * i + m] = v;
+}
+
+template <typename R>
+struct Push2Args {
+  SpeciesDev<R> sp[2];          // with oy
+  const long long* count;       // [2] particles per species as of the last sort
+  int tiles0;                   // work-groups of species 0
+  int ntiles;
+  Fields2Dev<R> f;              // E^n, B^n
+  unsigned long long* J[3];     // Jx [(nx + 2) ny], Jy, Jz [(nx + 3) ny] (node + 1)
+  double* acc;                  // [tile][4] cumulative: E_rad, E_esc_e, E_esc_i, n_stiff
+  int* flags;                   // [0]: non-finite seen
+  int nx, ny, ysh;
+  R cfl;                        // dt / dx = dt / dy
+  R dt;
+  R eps;
+  R qh[2];
+  int Z[2];
+  double mass[2];
+  int rr0;
+  int comp;
+  R sw;                         // 256 / w_ref
+  int qw_ref[2];
+};
+
+template <typename R>
+struct P2 {
+  int c;
+  R ox, oy, ux, uy, uz, w;
+  float rx, ry, rz;
+};
+
+// loads of particle i (cell already known); past the end, particle n - 1
+// is read instead and the cell says removed
+template <typename R, bool COMP>
+__device__ __forceinline__ P2<R> load2(const SpeciesDev<R>& sp, int i, int n, int c) {
+  P2<R> d;
+  const unsigned ui = (unsigned)(i < n ? i : n - 1);
+  d.c = c;
+  d.ox = ld(sp.off, ui);
+  d.oy = ld(sp.oy, ui);
+  d.ux = ld(sp.ux, ui);
+  d.uy = ld(sp.uy, ui);
+  d.uz = ld(sp.uz, ui);
+  d.w = ld(sp.w, ui);
+  if (COMP) {
+    d.rx = ld(sp.rx, ui);
+    d.ry = ld(sp.ry, ui);
+    d.rz = ld(sp.rz, ui);
+  } else {
+    d.rx = d.ry = d.rz = 0.f;
+  }
+  return d;
+}
+
+// E^n, B^n at a particle: bilinear weights of each component at its own
+// staggered position
+template <typename R>
+__device__ __forceinline__ void gather2(const Fields2Dev<R>& f, int ny, int ix, int iy, R ox, R oy,
+                                        R& ex, R& ey, R& ez, R& bx, R& by, R& bz) {
+  const unsigned j0 = (unsigned)iy, j1 = iy + 1 == ny ? 0u : (unsigned)(iy + 1);
+  const bool gb = oy >= R(0.5);                 // half-rows g0, g0 + 1 around the particle
+  const unsigned g0 = gb ? j0 : (iy == 0 ? (unsigned)(ny - 1) : j0 - 1), g1 = gb ? j1 : j0;
+  const R fy = gb ? oy - R(0.5) : oy + R(0.5);
+  const bool hb = ox >= R(0.5);                 // half-nodes h0, h0 + 1
+  const R fx = hb ? ox - R(0.5) : ox + R(0.5);
+  const unsigned n0 = (unsigned)ix * (unsigned)ny, n1 = n0 + (unsigned)ny;
+  const unsigned q0 = n0 + (hb ? (unsigned)ny : 0u), q1 = q0 + (unsigned)ny;
+  const R wx0 = R(1) - ox, wy0 = R(1) - oy, vx0 = R(1) - fx, vy0 = R(1) - fy;
+  {
+    const R a = ld(f.ez, n0 + j0), b = ld(f.ez, n0 + j1), c = ld(f.ez, n1 + j0), d = ld(f.ez, n1 + j1);
+    ez = wx0 * (wy0 * a + oy * b) + ox * (wy0 * c + oy * d);
+  }
+  {
+    const NH<R> a = ld(f.nh, n0 + g0), b = ld(f.nh, n0 + g1), c = ld(f.nh, n1 + g0),
+                d = ld(f.nh, n1 + g1);
+    ey = wx0 * (vy0 * a.ey + fy * b.ey) + ox * (vy0 * c.ey + fy * d.ey);
+    bx = wx0 * (vy0 * a.bx + fy * b.bx) + ox * (vy0 * c.bx + fy * d.bx);
+  }
+  {
+    const HN<R> a = ld(f.hn, q0 + j0), b = ld(f.hn, q0 + j1), c = ld(f.hn, q1 + j0),
+                d = ld(f.hn, q1 + j1);
+    ex = vx0 * (wy0 * a.ex + oy * b.ex) + fx * (wy0 * c.ex + oy * d.ex);
+    by = vx0 * (wy0 * a.by + oy * b.by) + fx * (wy0 * c.by + oy * d.by);
+  }
+  {
+    const R a = ld(f.bz, q0 + g0), b = ld(f.bz, q0 + g1), c = ld(f.bz, q1 + g0), d = ld(f.bz, q1 + g1);
+    bz = vx0 * (vy0 * a + fy * b) + fx * (vy0 * c + fy * d);
+  }
+}
+
+// Position update of the 2D contract: the 1D arithmetic in x and in y.
+template <typename R>
+__device__ __forceinline__ void contract_move2(R ux, R uy, R uz, R ox, R oy, R cfl, R& g, R& vz,
+                                               R& ox1, R& oy1, R& sx, R& sy) {
+#pragma clang fp contract(off)
+  g = sqrt_rn_ge1(((R(1) + ux * ux) + uy * uy) + uz * uz);
+  const R ig = rcp_rn_ge1(g);
+  const R vx = ux * ig, vy = uy * ig;
+  vz = uz * ig;
+  R s = ox + vx * cfl;
+  R fl = floor(s);
+  ox1 = s - fl;
+  if (ox1 >= R(1)) {
+    ox1 = R(0);
+    fl += R(1);
+  }
+  sx = fl;
+  s = oy + vy * cfl;
+  fl = floor(s);
+  oy1 = s - fl;
+  if (oy1 >= R(1)) {
+    oy1 = R(0);
+    fl += R(1);
+  }
+  sy = fl;
+}
+
+// 12-bit weights of one direction on the nodes (old cell - 1) .. (old cell + 2)
+template <typename R>
+__device__ __forceinline__ void shapes2(R o, R o1, int sh, int (&S0)[4], int (&S1)[4]) {
+  const int q0 = (int)(o * R(k2One)), q1 = (int)(o1 * R(k2One));
+  S0[0] = 0;
+  S0[1] = k2One - q0;
+  S0[2] = q0;
+  S0[3] = 0;
+  S1[0] = sh < 0 ? k2One - q1 : 0;
+  S1[1] = sh == 0 ? k2One - q1 : (sh < 0 ? q1 : 0);
+  S1[2] = sh > 0 ? k2One - q1 : (sh == 0 ? q1 : 0);
+  S1[3] = sh > 0 ? q1 : 0;
+}
+
+// The fixed-point Esirkepov terms of one move (see the 2D deposition
+// contract): t[a * 4 + b] Jx on face a + 1/2 (a < 3) and row b,
+// t[12 + a * 3 + b] Jy on node a and half-row b + 1/2 (b < 3),
+// t[24 + a * 4 + b] Jz on node a and row b; a, b count from (old cell - 1).
+// Every term is below 2^25, so 24-bit multiplies are exact.
+template <typename R>
+__device__ __forceinline__ void deposit2_terms(R ox, R oy, R ox1, R oy1, int sx, int sy, R vz,
+                                               int (&t)[k2Terms]) {
+  int X0[4], X1[4], Y0[4], Y1[4];
+  shapes2<R>(ox, ox1, sx, X0, X1);
+  shapes2<R>(oy, oy1, sy, Y0, Y1);
+  int Cx[3], Cy[3];
+  Cx[0] = X0[0] - X1[0];
+  Cy[0] = Y0[0] - Y1[0];
+#pragma unroll
+  for (int a = 1; a < 3; ++a) {
+    Cx[a] = Cx[a - 1] + (X0[a] - X1[a]);
+    Cy[a] = Cy[a - 1] + (Y0[a] - Y1[a]);
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) t[a * 4 + b] = __mul24(Cx[a], Y0[b] + Y1[b]);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) t[12 + a * 3 + b] = __mul24(X0[a] + X1[a], Cy[b]);
+  const int vz12 = (int)rint(vz * R(k2One));
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      t[24 + a * 4 + b] = __mul24(vz12, (__mul24(X0[a], Y0[b]) + __mul24(X1[a], Y1[b])) >> k2Q);
+}
+
+// LDS current box of one tile: columns xmn .. xmn + 7 (Jx: half-nodes
+// h = xmn + c; Jy, Jz: node index xmn + c, i.e. node xmn - 1 + c), rows
+// jbase .. jbase + BY - 1 (mod ny); slot (comp, r, c) at comp * 8 BY + 8 r + c
+struct Box2 {
+  unsigned long long* lds;
+  int xmn, jbase, BY;
+  bool use;
+};
+
+// inclusive scan over the 16 lanes of each row; lane 15 of a row ends with
+// the row's sum (all lanes of the wave active)
+__device__ __forceinline__ int row_sum16(int v) {
+  v += row_shr<1>(0, v);
+  v += row_shr<2>(0, v);
+  v += row_shr<4>(0, v);
+  v += row_shr<8>(0, v);
+  return v;
+}
+
+// Deposit the terms of the wave's particles.  Lanes with the reference
+// charge weight are grouped by old cell: per pass, each 16-lane row takes
+// the cell of its first pending lane, sums the terms of its lanes in that
+// cell, and its last lane adds the 40 sums to the box (or to HBM when the
+// tile has no box); passes repeat until every lane is done.  Other weights
+// (none in uniform-weight runs) add their own terms to HBM.
+template <typename R>
+__device__ __forceinline__ void deposit2_wave(const Push2Args<R>& a, const Box2& bx, int cell,
+                                              bool dep, int qw, int qw_ref, const int (&t)[k2Terms]) {
+  const int lane = threadIdx.x & 63, row = lane >> 4;
+  const int ymask = (1 << a.ysh) - 1, ny = a.ny;
+  unsigned long long act = __ballot(dep && qw == qw_ref);
+  while (act) {
+    int Lr[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const unsigned m = (unsigned)(act >> (16 * r)) & 0xffffu;
+      Lr[r] = m ? __builtin_amdgcn_readlane(cell, 16 * r + __builtin_ctz(m)) : kDead;
+    }
+    const int myL = row == 0 ? Lr[0] : (row == 1 ? Lr[1] : (row == 2 ? Lr[2] : Lr[3]));
+    const bool mine = ((act >> lane) & 1ull) && cell == myL;
+    const bool writer = (lane & 15) == 15 && myL != kDead;
+    // addresses of the writer lanes: row offsets of the leader cell's stencil
+    const int lx = myL >> a.ysh, ly = myL & ymask;
+    int rb[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      int r = ly - 1 + b - (bx.use ? bx.jbase : 0);
+      r += r < 0 ? ny : 0;
+      r -= r >= ny ? ny : 0;
+      rb[b] = r;
+    }
+    const int c0 = lx - bx.xmn;
+#pragma unroll
+    for (int q = 0; q < k2Terms; ++q) {
+      const int v = row_sum16(mine ? t[q] : 0);
+      // (comp, column offset a, row b) of term q
+      const int comp = q < 12 ? 0 : (q < 24 ? 1 : 2);
+      const int ca = q < 12 ? q / 4 : (q < 24 ? (q - 12) / 3 : (q - 24) / 4);
+      const int rbq = q < 12 ? q % 4 : (q < 24 ? (q - 12) % 3 : (q - 24) % 4);
+      if (writer) {
+        if (bx.use) {
+          atomicAdd(bx.lds + comp * 8 * bx.BY + rb[rbq] * 8 + c0 + ca,
+                    (unsigned long long)(long long)v);
+        } else {
+          atomicAdd(a.J[comp] + (size_t)(lx + ca) * ny + rb[rbq],
+                    (unsigned long long)((long long)v * qw_ref));
+        }
+      }
+    }
+    act &= ~__ballot(mine);
+  }
+  if (dep && qw != qw_ref) {
+    const int lx = cell >> a.ysh, ly = cell & ymask;
+#pragma unroll
+    for (int q = 0; q < k2Terms; ++q) {
+      const int comp = q < 12 ? 0 : (q < 24 ? 1 : 2);
+      const int ca = q < 12 ? q / 4 : (q < 24 ? (q - 12) / 3 : (q - 24) / 4);
+      const int rbq = q < 12 ? q % 4 : (q < 24 ? (q - 12) % 3 : (q - 24) % 4);
+      int r = ly - 1 + rbq;
+      r += r < 0 ? ny : 0;
+      r -= r >= ny ? ny : 0;
+      atomicAdd(a.J[comp] + (size_t)(lx + ca) * ny + r, (unsigned long long)((long long)t[q] * qw));
+    }
+  }
+}
+
+struct Acc2 {
+  float rad, esc, stiff;
+};
+
+// One particle: gather, Boris with RR, 2D move, stores; fills the deposit
+// terms (zero and dep = false for removed particles).
+template <typename R, bool RR, bool COMP>
+__device__ __forceinline__ void push2_particle(const Push2Args<R>& a, const SpeciesDev<R>& sp, int s,
+                                               unsigned ui, const P2<R>& pd, int (&t)[k2Terms],
+                                               int& qw, bool& dep, Acc2& acc) {
+  dep = false;
+  qw = 0;
+#pragma unroll
+  for (int q = 0; q < k2Terms; ++q) t[q] = 0;
+  if (pd.c == kDead) return;
+  const int ymask = (1 << a.ysh) - 1;
+  const int ix = pd.c >> a.ysh, iy = pd.c & ymask;
+  R ex, ey, ez, bx, by, bz;
+  gather2<R>(a.f, a.ny, ix, iy, pd.ox, pd.oy, ex, ey, ez, bx, by, bz);
+  float rx = pd.rx, ry = pd.ry, rz = pd.rz;
+  MomentumOut<R> mo;
+  momentum_step<R, RR, COMP, false, true>(pd.ux, pd.uy, pd.uz, ex, ey, ez, by, bz, a.qh[s],
+                                          a.eps * a.dt, FieldRates<R>{}, rx, ry, rz, acc.stiff, mo,
+                                          bx);
+  R g, vz, ox1, oy1, shx, shy;
+  contract_move2<R>(mo.nx, mo.ny, mo.nz, pd.ox, pd.oy, a.cfl, g, vz, ox1, oy1, shx, shy);
+  if (!(fabs(shx) < R(4)) || !(fabs(shy) < R(4)) || !(g < R(1e30))) {
+    st(sp.cell, ui, kDead);
+    atomicOr(a.flags, 1);
+    return;
+  }
+  const int sx = (int)shx, sy = (int)shy;
+  qw = a.Z[s] * (int)rint(pd.w * a.sw);
+  dep = true;
+  deposit2_terms<R>(pd.ox, pd.oy, ox1, oy1, sx, sy, vz, t);
+  if (RR) {
+    const R num = mo.ddx * (R(2) * mo.Lx + mo.ddx) + mo.ddy * (R(2) * mo.Ly + mo.ddy) +
+                  mo.ddz * (R(2) * mo.Lz + mo.ddz);
+    acc.rad -= (float)(pd.w * num * rcp(mo.gL + g));
+  }
+  const int ix1 = ix + sx;
+  int iy1 = iy + sy;
+  iy1 += iy1 < 0 ? a.ny : 0;
+  iy1 -= iy1 >= a.ny ? a.ny : 0;
+  if (ix1 < 0 || ix1 >= a.nx) {
+    st(sp.cell, ui, kDead);
+    acc.esc += (float)(pd.w * (R)a.mass[s] * (g - R(1)));
+  } else {
+    st(sp.cell, ui, (ix1 << a.ysh) | iy1);
+    st(sp.off, ui, ox1);
+    st(sp.oy, ui, oy1);
+  }
+  st(sp.ux, ui, mo.nx);
+  st(sp.uy, ui, mo.ny);
+  st(sp.uz, ui, mo.nz);
+  if (COMP) {
+    st(sp.rx, ui, rx);
+    st(sp.ry, ui, ry);
+    st(sp.rz, ui, rz);
+  }
+}
+
+template <typename R, bool RR, bool COMP>
+__device__ __forceinline__ void push2_tile(const Push2Args<R>& a, int s, int tile, int n, int base,
+                                           unsigned long long* lds) {
+  __shared__ int s_red[4][kThreads / kLanes];
+  __shared__ int s_jref;
+  __shared__ double s_acc[3][kThreads / kLanes];
+  const SpeciesDev<R> sp = a.sp[s];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int ny = a.ny, ymask = (1 << a.ysh) - 1;
+
+  int cl[k2PPT];
+#pragma unroll
+  for (int k = 0; k < k2PPT; ++k) {
+    const int i = base + k * kThreads + tid;
+    cl[k] = i < n ? ld(sp.cell, (unsigned)i) : kDead;
+  }
+  // the tile's rows as an arc of the periodic y range around a reference
+  // row (the first live particle of thread 0)
+  if (tid == 0) {
+    int jr = 0;
+#pragma unroll
+    for (int k = k2PPT - 1; k >= 0; --k)
+      if (cl[k] != kDead) jr = cl[k] & ymask;
+    s_jref = jr;
+  }
+  __syncthreads();
+  const int jref = s_jref, half = ny >> 1;
+  int xmn = INT_MAX, xmx = INT_MIN, dmn = INT_MAX, dmx = INT_MIN;
+#pragma unroll
+  for (int k = 0; k < k2PPT; ++k) {
+    const int c = cl[k];
+    if (c != kDead) {
+      const int x = c >> a.ysh;
+      int d = (c & ymask) - jref;
+      d += d < -half ? ny : 0;
+      d -= d >= ny - half ? ny : 0;
+      xmn = min(xmn, x);
+      xmx = max(xmx, x);
+      dmn = min(dmn, d);
+      dmx = max(dmx, d);
+    }
+  }
+  xmn = wave_min_dpp(xmn);
+  xmx = wave_max_dpp(xmx);
+  dmn = wave_min_dpp(dmn);
+  dmx = wave_max_dpp(dmx);
+  if (lane == 0) {
+    s_red[0][wid] = xmn;
+    s_red[1][wid] = xmx;
+    s_red[2][wid] = dmn;
+    s_red[3][wid] = dmx;
+  }
+  __syncthreads();
+  xmn = min(min(s_red[0][0], s_red[0][1]), min(s_red[0][2], s_red[0][3]));
+  xmx = max(max(s_red[1][0], s_red[1][1]), max(s_red[1][2], s_red[1][3]));
+  dmn = min(min(s_red[2][0], s_red[2][1]), min(s_red[2][2], s_red[2][3]));
+  dmx = max(max(s_red[3][0], s_red[3][1]), max(s_red[3][2], s_red[3][3]));
+  if (xmn > xmx) return;  // every particle of the tile was removed (block-uniform)
+
+  Box2 bx;
+  bx.lds = lds;
+  bx.xmn = xmn;
+  bx.use = xmx - xmn <= k2Cols - 4;
+  const int span = dmx - dmn + 4;  // rows of the stencils: arc plus one below and two above
+  if (span < ny && span <= k2MaxRows) {
+    bx.BY = span;
+    int jb = jref + dmn - 1;
+    jb += jb < 0 ? ny : 0;
+    jb -= jb >= ny ? ny : 0;
+    bx.jbase = jb;
+  } else {
+    bx.BY = ny;  // every row: stencil rows wrap onto the box
+    bx.jbase = 0;
+    bx.use = bx.use && ny <= k2MaxRows;
+  }
+  const int E = 3 * k2Cols * bx.BY;
+  if (bx.use)
+    for (int e = tid; e < E; e += kThreads) lds[e] = 0ull;
+  __syncthreads();
+
+  Acc2 acc{0.f, 0.f, 0.f};
+  const int qw_ref = a.qw_ref[s];
+  P2<R> cur = load2<R, COMP>(sp, base + tid, n, cl[0]);
+#pragma unroll 2
+  for (int k = 0; k < k2PPT; ++k) {
+    const int i = base + k * kThreads + tid;
+    P2<R> nxt;
+    if (k + 1 < k2PPT) nxt = load2<R, COMP>(sp, i + kThreads, n, cl[k + 1]);
+    int t[k2Terms], qw;
+    bool dep;
+    push2_particle<R, RR, COMP>(a, sp, s, (unsigned)i, cur, t, qw, dep, acc);
+    deposit2_wave<R>(a, bx, cur.c, dep, qw, qw_ref, t);
+    if (k + 1 < k2PPT) cur = nxt;
+  }
+
+  const double r0 = wave_sum_dpp((double)acc.rad), r1 = wave_sum_dpp((double)acc.esc),
+               r2 = wave_sum_dpp((double)acc.stiff);
+  if (lane == 0) {
+    s_acc[0][wid] = r0;
+    s_acc[1][wid] = r1;
+    s_acc[2][wid] = r2;
+  }
+  __syncthreads();
+  if (bx.use) {
+    const int BY8 = 8 * bx.BY;
+    for (int e = tid; e < E; e += kThreads) {
+      const long long v = (long long)lds[e];
+      if (v) {
+        const int comp = e >= 2 * BY8 ? 2 : (e >= BY8 ? 1 : 0);
+        const int rem = e - comp * BY8;
+        const int r = rem >> 3, c = rem & 7;
+        int gy = bx.jbase + r;
+        gy -= gy >= ny ? ny : 0;
+        atomicAdd(a.J[comp] + (size_t)(xmn + c) * ny + gy, (unsigned long long)(v * qw_ref));
+      }
+    }
+  }
+  if (tid == 0) {
+    double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+    for (int w = 0; w < kThreads / kLanes; ++w) {
+      t0 += s_acc[0][w];
+      t1 += s_acc[1][w];
+      t2 += s_acc[2][w];
+    }
+    double* A = a.acc + 4 * (size_t)tile;
+    unsafeAtomicAdd(A + 0, t0);
+    unsafeAtomicAdd(A + 1 + s, t1);
+    unsafeAtomicAdd(A + 3, t2);
+  }
+}
+
+// one work-group per tile
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_push2(Push2Args<R> a) {
+  __shared__ unsigned long long lds[k2Slots];
+  const int tile = (int)blockIdx.x;
+  const int s = tile < a.tiles0 ? 0 : 1;
+  const int tl = s ? tile - a.tiles0 : tile;
+  const int n = (int)a.count[s];
+  const int base = tl * k2Tile;
+  if (base >= n) return;
+  if (s == 0 && a.rr0) {
+    if (a.comp)
+      push2_tile<R, true, true>(a, s, tile, n, base, lds);
+    else
+      push2_tile<R, true, false>(a, s, tile, n, base, lds);
+  } else {
+    push2_tile<R, false, false>(a, s, tile, n, base, lds);
+  }
+}
+
+// cell sort of 2D particles: the 1D passes, with the y offset moved too
+template <typename R>
+__global__ __launch_bounds__(kSortThreads) void k_sort_scatter2(SortArgs<R> p) {
+  sort_scatter_block<R, true>(p, (int)blockIdx.x);
+}
+
+// ---------------------------------------------------------------- fields
+template <typename R>
+struct Field2Args {
+  Fields2Dev<R> f;
+  const long long* J[3];          // current of this step
+  unsigned long long* Jnext[3];   // current of the next step, zeroed by k_field2_e
+  long long* cont;                // [(nx + 1) ny] integer charge carried by the current
+  double* flux;                   // [3][ny] per row: E_in, E_out_left, E_out_right
+  long long* step;                // device step counter
+  int nx, ny;
+  R a, ha, dt;                    // dt/dx, dt/(2 dx), dt
+  double dtd, dy;
+  double sJ, sJz;                 // fixed point -> current density (Jx, Jy; Jz)
+  double ay, az;                  // incident amplitude per component
+  double tr, tf, tl;              // envelope (1/omega)
+  double waist, yc;               // transverse profile exp(-((y - yc) / waist)^2); waist 0: flat
+};
+
+// B^n -> B^{n+1/2} (or B^{n+1/2} -> B^{n+1}) at every interior position; one
+// thread per (column X = 0..nx+1, row j); the last call of a step advances
+// the step counter
+template <typename R>
+__global__ __launch_bounds__(256) void k_field2_b(Field2Args<R> p, int tick) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int ny = p.ny, n = p.nx;
+  if (t >= (long long)(n + 2) * ny) return;
+  const int X = (int)(t / ny), j = (int)(t - (long long)X * ny);
+  const int jp = j + 1 == ny ? 0 : j + 1;
+  const R ha = p.ha;
+  const size_t c = (size_t)X * ny;
+  if (X >= 1 && X <= n) {  // half-node h = X: B_z (half-row j), B_y (row j)
+    const R ey1 = p.f.nh[c + j].ey, ey0 = p.f.nh[c - ny + j].ey;
+    const R ex0 = p.f.hn[c + j].ex, ex1 = p.f.hn[c + jp].ex;
+    p.f.bz[c + j] -= ha * ((ey1 - ey0) - (ex1 - ex0));
+    const R ez1 = p.f.ez[c + j], ez0 = p.f.ez[c - ny + j];
+    st_member<R>(p.f.hn, c + j, 1, p.f.hn[c + j].by + ha * (ez1 - ez0));
+  }
+  if (X <= n) {  // node i = X: B_x (half-row j)
+    const R ez0 = p.f.ez[c + j], ez1 = p.f.ez[c + jp];
+    st_member<R>(p.f.nh, c + j, 1, p.f.nh[c + j].bx - ha * (ez1 - ez0));
+  }
+  if (tick && t == 0) *p.step += 1;
+}
+
+__device__ __forceinline__ double profile2(double y, double yc, double waist) {
+  if (waist <= 0.0) return 1.0;
+  const double u = (y - yc) / waist;
+  return exp(-u * u);
+}
+
+// E^n -> E^{n+1} with J^{n+1/2}, the boundary guards at t_{n+1/2}, per-row
+// boundary fluxes, the running integer charge, and the next current cleared
+template <typename R>
+__global__ __launch_bounds__(256) void k_field2_e(Field2Args<R> p) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int ny = p.ny, n = p.nx;
+  if (t >= (long long)(n + 2) * ny) return;
+  const int X = (int)(t / ny), j = (int)(t - (long long)X * ny);
+  const int jm = j == 0 ? ny - 1 : j - 1;
+  const R a = p.a, dt = p.dt;
+  const size_t c = (size_t)X * ny;
+  p.Jnext[0][c + j] = 0ull;
+  p.Jnext[1][c + j] = 0ull;
+  p.Jnext[2][c + j] = 0ull;
+  if (X == n + 1) {
+    p.Jnext[1][c + ny + j] = 0ull;
+    p.Jnext[2][c + ny + j] = 0ull;
+  }
+  if (X >= 1 && X <= n) {  // E_x at half-node h = X, row j
+    const R jx = (R)((double)p.J[0][c + j] * p.sJ);
+    const R ex = p.f.hn[c + j].ex + (a * (p.f.bz[c + j] - p.f.bz[c + jm]) - dt * jx);
+    st_member<R>(p.f.hn, c + j, 0, ex);
+  }
+  if (X > n) return;
+  // node i = X: E_y (half-row j), E_z (row j)
+  const R jy = (R)((double)p.J[1][c + ny + j] * p.sJ);
+  const R jz = (R)((double)p.J[2][c + ny + j] * p.sJz);
+  const NH<R> e = p.f.nh[c + j];
+  const R ez = p.f.ez[c + j];
+  R bz0 = p.f.bz[c + j], bz1 = p.f.bz[c + ny + j];
+  R by0 = p.f.hn[c + j].by, by1 = p.f.hn[c + ny + j].by;
+  const R bxm = p.f.nh[c + jm].bx;
+  const R d = R(1) + a;
+  double ey_in = 0.0, ez_in = 0.0;
+  if (X == 0) {  // left guards (h = 0) with the incident wave
+    const double th = ((double)*p.step + 0.5) * p.dtd;
+    const double f = envelope(th, p.tr, p.tf, p.tl);
+    ey_in = p.ay * f * sin(th) * profile2((j + 0.5) * p.dy, p.yc, p.waist);
+    ez_in = p.az * f * cos(th) * profile2((double)j * p.dy, p.yc, p.waist);
+    bz0 = (R(4) * (R)ey_in - R(2) * e.ey - (R(1) - a) * bz1 + dt * jy) / d;
+    by0 = (R(2) * ez - (R(1) - a) * by1 - dt * jz - R(4) * (R)ez_in) / d;
+    p.f.bz[c + j] = bz0;
+    st_member<R>(p.f.hn, c + j, 1, by0);
+  }
+  if (X == n) {  // right guards (h = n + 1)
+    bz1 = (R(2) * e.ey - (R(1) - a) * bz0 - dt * jy) / d;
+    by1 = (R(-2) * ez - (R(1) - a) * by0 + dt * jz) / d;
+    p.f.bz[c + ny + j] = bz1;
+    st_member<R>(p.f.hn, c + ny + j, 1, by1);
+  }
+  const R ey_new = e.ey - (a * (bz1 - bz0) + dt * jy);
+  const R ez_new = ez + (a * ((by1 - by0) - (e.bx - bxm)) - dt * jz);
+  st_member<R>(p.f.nh, c + j, 0, ey_new);
+  p.f.ez[c + j] = ez_new;
+  if (X == 0) {
+    const double eyl = 0.5 * ((double)e.ey + (double)ey_new), ezl = 0.5 * ((double)ez + (double)ez_new);
+    const double bzl = 0.5 * ((double)bz0 + (double)bz1), byl = 0.5 * ((double)by0 + (double)by1);
+    const double L1 = eyl - bzl, L2 = ezl + byl;
+    p.flux[j] += p.dtd * p.dy * (ey_in * ey_in + ez_in * ez_in);
+    p.flux[ny + j] += p.dtd * p.dy * 0.25 * (L1 * L1 + L2 * L2);
+  }
+  if (X == n) {
+    const double eyr = 0.5 * ((double)e.ey + (double)ey_new), ezr = 0.5 * ((double)ez + (double)ez_new);
+    const double bzr = 0.5 * ((double)bz0 + (double)bz1), byr = 0.5 * ((double)by0 + (double)by1);
+    const double R1 = eyr + bzr, R2 = ezr - byr;
+    p.flux[2 * ny + j] += p.dtd * p.dy * 0.25 * (R1 * R1 + R2 * R2);
+  }
+  // charge moved onto node (X, j) by this step's current
+  const long long div = (p.J[0][c + ny + j] - p.J[0][c + j]) + (p.J[1][c + ny + j] - p.J[1][c + ny + jm]);
+  p.cont[c + j] -= div;
+}
+
+// ---------------------------------------------------------------- init
+// Quiet start: particle i of the foil (cells column by column, rows fastest;
+// k = i mod ppc, kx = k / ppc_y, ky = k mod ppc_y) at offsets
+// ((kx + 1/2) + jitter (U_2i - 1/2)) / ppc_x, ((ky + 1/2) + jitter (U_2i+1 - 1/2)) / ppc_y
+template <typename R>
+__global__ void k_init2(SpeciesDev<R> e, SpeciesDev<R> ion, long long n, int c0, int ny, int ysh,
+                        int ppcx, int ppcy, unsigned long long seed, double jitter, R w) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int ppc = ppcx * ppcy;
+  const long long q = i / ppc;
+  const int k = (int)(i - q * ppc);
+  const int kx = k / ppcy, ky = k - kx * ppcy;
+  const int ix = c0 + (int)(q / ny), iy = (int)(q % ny);
+  const R U1 = (R)(splitmix64(seed, 2ull * (unsigned long long)i) >> 40) * R(1.0 / 16777216.0);
+  const R U2 = (R)(splitmix64(seed, 2ull * (unsigned long long)i + 1ull) >> 40) * R(1.0 / 16777216.0);
+  R ox = ((R)kx + R(0.5) + (R)jitter * (U1 - R(0.5))) / (R)ppcx;
+  R oy = ((R)ky + R(0.5) + (R)jitter * (U2 - R(0.5))) / (R)ppcy;
+  if (!(ox < R(1))) ox = R(0);
+  if (!(oy < R(1))) oy = R(0);
+  SpeciesDev<R> sp[2] = {e, ion};
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    sp[s].cell[i] = (ix << ysh) | iy;
+    sp[s].off[i] = ox;
+    sp[s].oy[i] = oy;
+    sp[s].ux[i] = R(0);
+    sp[s].uy[i] = R(0);
+    sp[s].uz[i] = R(0);
+    sp[s].w[i] = w;
+    if (sp[s].rx) {
+      sp[s].rx[i] = 0.f;
+      sp[s].ry[i] = 0.f;
+      sp[s].rz[i] = 0.f;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- diagnostics
+constexpr int k2DiagBlocks = 512;
+
+template <typename R>
+struct Diag2Args {
+  SpeciesDev<R> sp[2];
+  const long long* count;
+  Fields2Dev<R> f;
+  const long long* cont;
+  long long* rho;       // [(nx + 1) ny] integer charge of the particles, zeroed by the caller
+  double* part;         // [6][k2DiagBlocks]: K_e, K_i, U_Ex, U_Et, U_B, gauss max
+  long long* ipart;     // [3][k2DiagBlocks]: alive e, alive i, continuity max
+  int nx, ny, ysh;
+  double mass[2];
+  int Z[2];
+  R sw;
+  double dx, srho;      // integer charge -> density
+};
+
+// kinetic energy, alive counts and the integer charge 2 qw S_x S_y
+template <typename R>
+__global__ __launch_bounds__(256) void k_diag2_particles(Diag2Args<R> p) {
+  __shared__ double sh[4];
+  const int s = blockIdx.x < k2DiagBlocks ? 0 : 1;
+  const int b = blockIdx.x - s * k2DiagBlocks;
+  const long long n = p.count[s];
+  const SpeciesDev<R> sp = p.sp[s];
+  const int ymask = (1 << p.ysh) - 1, ny = p.ny;
+  double ke = 0.0;
+  long long alive = 0;
+  for (long long i = (long long)b * 256 + threadIdx.x; i < n; i += (long long)k2DiagBlocks * 256) {
+    const int c = sp.cell[i];
+    if (c == kDead) continue;
+    const double ux = sp.ux[i], uy = sp.uy[i], uz = sp.uz[i];
+    ke += (double)sp.w[i] * p.mass[s] * (sqrt(1.0 + ux * ux + uy * uy + uz * uz) - 1.0);
+    alive += 1;
+    const int ix = c >> p.ysh, iy = c & ymask, iy1 = iy + 1 == ny ? 0 : iy + 1;
+    const long long qx = (long long)(sp.off[i] * R(k2One)), qy = (long long)(sp.oy[i] * R(k2One));
+    const long long qw = 2ll * p.Z[s] * (long long)rint(sp.w[i] * p.sw);
+    unsigned long long* r = (unsigned long long*)p.rho;
+    const size_t c0 = (size_t)ix * ny, c1 = c0 + ny;
+    atomicAdd(r + c0 + iy, (unsigned long long)(qw * (k2One - qx) * (k2One - qy)));
+    atomicAdd(r + c0 + iy1, (unsigned long long)(qw * (k2One - qx) * qy));
+    atomicAdd(r + c1 + iy, (unsigned long long)(qw * qx * (k2One - qy)));
+    atomicAdd(r + c1 + iy1, (unsigned long long)(qw * qx * qy));
+  }
+  const double t = block_sum(ke, sh);
+  __shared__ long long sa[4];
+  const long long na = wave_sum((long long)alive);
+  if ((threadIdx.x & 63) == 0) sa[threadIdx.x >> 6] = na;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    p.part[s * k2DiagBlocks + b] = t;
+    p.ipart[s * k2DiagBlocks + b] = sa[0] + sa[1] + sa[2] + sa[3];
+  }
+}
+
+// field energies, Gauss residual from the fields and the particles' charge,
+// and the largest difference between that charge and the one the current
+// carried (exact integers: expect 0)
+template <typename R>
+__global__ __launch_bounds__(256) void k_diag2_fields(Diag2Args<R> p) {
+  __shared__ double sh[4];
+  __shared__ long long sm[4];
+  const int ny = p.ny, n = p.nx;
+  double ux = 0.0, ue = 0.0, ub = 0.0, gmax = 0.0;
+  long long cmax = 0;
+  const long long tot = (long long)(n + 2) * ny;
+  for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < tot;
+       t += (long long)k2DiagBlocks * 256) {
+    const int X = (int)(t / ny), j = (int)(t - (long long)X * ny);
+    const size_t c = (size_t)X * ny;
+    if (X <= n) {
+      const double wn = (X == 0 || X == n) ? 0.5 : 1.0;
+      const NH<R> e = p.f.nh[c + j];
+      const double ey = e.ey, ez = p.f.ez[c + j], bxv = e.bx;
+      ue += wn * (ey * ey + ez * ez);
+      ub += wn * bxv * bxv;
+      long long dc = p.cont[c + j] - p.rho[c + j];
+      dc = dc < 0 ? -dc : dc;
+      cmax = dc > cmax ? dc : cmax;
+      if (X >= 1 && X <= n - 1) {
+        const int jm = j == 0 ? ny - 1 : j - 1;
+        const double divE = ((double)p.f.hn[c + ny + j].ex - (double)p.f.hn[c + j].ex) / p.dx +
+                            ((double)e.ey - (double)p.f.nh[c + jm].ey) / p.dx;
+        const double r = fabs(divE - (double)p.rho[c + j] * p.srho);
+        gmax = r > gmax ? r : gmax;
+      }
+    }
+    if (X >= 1 && X <= n) {
+      const HN<R> h = p.f.hn[c + j];
+      const double exv = h.ex, byv = h.by, bzv = p.f.bz[c + j];
+      ux += exv * exv;
+      ub += byv * byv + bzv * bzv;
+    }
+  }
+  const double a2 = 0.5 * p.dx * p.dx;
+  const double t0 = block_sum(ux, sh), t1 = block_sum(ue, sh), t2 = block_sum(ub, sh);
+  double g = gmax;
+  long long cm = cmax;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double v = __shfl_xor(g, o);
+    g = v > g ? v : g;
+    const long long w = __shfl_xor(cm, o);
+    cm = w > cm ? w : cm;
+  }
+  __shared__ double sg[4];
+  if ((threadIdx.x & 63) == 0) {
+    sg[threadIdx.x >> 6] = g;
+    sm[threadIdx.x >> 6] = cm;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double gm = 0.0;
+    long long m = 0;
+    for (int w = 0; w < 4; ++w) {
+      gm = sg[w] > gm ? sg[w] : gm;
+      m = sm[w] > m ? sm[w] : m;
+    }
+    p.part[2 * k2DiagBlocks + blockIdx.x] = a2 * t0;
+    p.part[3 * k2DiagBlocks + blockIdx.x] = a2 * t1;
+    p.part[4 * k2DiagBlocks + blockIdx.x] = a2 * t2;
+    p.part[5 * k2DiagBlocks + blockIdx.x] = gm;
+    p.ipart[2 * k2DiagBlocks + blockIdx.x] = m;
+  }
+}
+
+struct Diag2OutDev {
+  double U_Ex, U_Et, U_B, K_e, K_i, E_rad, E_esc, n_stiff, gauss, E_in, E_ol, E_or;
+  long long cont_max, alive0, alive1;
+};
+
+__global__ __launch_bounds__(256) void k_diag2_final(const double* part, const long long* ipart,
+                                                     const double* acc, int tiles,
+                                                     const double* flux, int ny, Diag2OutDev* out) {
+  __shared__ double sh[256];
+  Diag2OutDev o{};
+  o.K_e = fixed_sum(part, k2DiagBlocks, 1, 0, sh);
+  o.K_i = fixed_sum(part + k2DiagBlocks, k2DiagBlocks, 1, 0, sh);
+  o.U_Ex = fixed_sum(part + 2 * k2DiagBlocks, k2DiagBlocks, 1, 0, sh);
+  o.U_Et = fixed_sum(part + 3 * k2DiagBlocks, k2DiagBlocks, 1, 0, sh);
+  o.U_B = fixed_sum(part + 4 * k2DiagBlocks, k2DiagBlocks, 1, 0, sh);
+  o.E_rad = fixed_sum(acc, tiles, 4, 0, sh);
+  o.E_esc = fixed_sum(acc, tiles, 4, 1, sh) + fixed_sum(acc, tiles, 4, 2, sh);
+  o.n_stiff = fixed_sum(acc, tiles, 4, 3, sh);
+  o.E_in = fixed_sum(flux, ny, 1, 0, sh);
+  o.E_ol = fixed_sum(flux + ny, ny, 1, 0, sh);
+  o.E_or = fixed_sum(flux + 2 * ny, ny, 1, 0, sh);
+  if (threadIdx.x == 0) {
+    for (int b = 0; b < k2DiagBlocks; ++b) {
+      o.alive0 += ipart[b];
+      o.alive1 += ipart[k2DiagBlocks + b];
+      o.cont_max = ipart[2 * k2DiagBlocks + b] > o.cont_max ? ipart[2 * k2DiagBlocks + b] : o.cont_max;
+      o.gauss = part[5 * k2DiagBlocks + b] > o.gauss ? part[5 * k2DiagBlocks + b] : o.gauss;
+    }
+    *out = o;
+  }
+}
+
+}  // namespace pic

@@ -1,4 +1,5 @@
-// Host side of the C ABI declared in include/pic.h: workspace carving,
+// Host side of the C ABI declared in include/pic.h (and, through
+// pic2d_host.inc at the end, include/pic2d.h): workspace carving,
 // validation, kernel launches, state I/O and per-kernel event timing.
 #include "pic.h"
 #include "kernels.hpp"
@@ -227,7 +228,8 @@ constexpr size_t kNoEvent = ~(size_t)0;
 // Events for a sampled launch: the kernel launch itself records them at its
 // start and end (hipExtLaunchKernel), so the measured time is the kernel's
 // execution without the queue time of separate event packets.
-pic_status ev_pick(pic_run* r, int kind, size_t* slot, hipEvent_t* a, hipEvent_t* b) {
+template <class Run>
+pic_status ev_pick(Run* r, int kind, size_t* slot, hipEvent_t* a, hipEvent_t* b) {
   *slot = kNoEvent;
   *a = *b = nullptr;
   if (!r->timing) return PIC_OK;
@@ -256,7 +258,8 @@ pic_status ev_pick(pic_run* r, int kind, size_t* slot, hipEvent_t* a, hipEvent_t
   return PIC_OK;
 }
 
-void ev_done(pic_run* r, size_t slot) {
+template <class Run>
+void ev_done(Run* r, size_t slot) {
   if (slot == kNoEvent) return;
   TimingRec& e = r->ev[slot];
   e.used = true;
@@ -1204,3 +1207,6 @@ void pic_batch_free(pic_batch* b) {
 }
 
 }  // extern "C"
+
+// The 2D3V entry points share this translation unit and its helpers.
+#include "pic2d_host.inc"

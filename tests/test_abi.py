@@ -1,4 +1,4 @@
-"""The C-ABI library loads and exports every entry point include/pic.h declares
+"""The C-ABI library loads and exports every entry point include/*.h declares
 (no GPU needed: nothing here launches a kernel)."""
 import ctypes as C
 import os
@@ -13,14 +13,17 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    txt = open(os.path.join(ROOT, "include", "pic.h")).read()
-    return sorted(set(re.findall(r"\b(pic_[a-z_]+)\s*\(", txt)))
+    inc = os.path.join(ROOT, "include")
+    txt = "".join(open(os.path.join(inc, f)).read() for f in sorted(os.listdir(inc))
+                  if f.endswith(".h"))
+    return sorted(set(re.findall(r"\b(pic(?:2d)?_[a-z_]+)\s*\(", txt)))
 
 
 def test_every_declared_symbol_is_exported_and_bound():
     lib = N.load()
     names = _declared()
-    assert len(names) >= 15
+    assert len(names) >= 30
+    assert "pic2d_push_deposit" in names
     for n in names:
         assert hasattr(lib, n), n
         assert n in N.SIGNATURES, f"{n} not declared in the binding"
@@ -94,3 +97,32 @@ def test_track_and_particle_reads_validate_on_the_host():
     assert call(args(n=0, p=None)) == N.PIC_OK
     sp = N.PicSpeciesState()
     assert lib.pic_get_particles(None, 0, 0, 1, C.byref(sp), None) == N.PIC_EINVAL
+
+
+def test_2d_config_validation_on_host():
+    from paper_1008_1685_amd.run2d import make_config
+    from workloads import preset2d
+    lib = N.load()
+    n = C.c_size_t()
+    sizes = {}
+    for name in ("d1", "d2"):
+        c = make_config(preset2d(name))
+        assert lib.pic2d_workspace_bytes(C.byref(c), C.byref(n)) == N.PIC_OK
+        sizes[name] = n.value
+    # d2: 4.2e6 particles per species in two buffers, 40 B each (electrons), plus grids
+    assert sizes["d2"] > 2 * 4.19e6 * (28 + 40) and sizes["d1"] < sizes["d2"]
+    for bad in (dict(cfl=0.6), dict(ppc_x=0), dict(x_foil=99.0), dict(box_y=0.01),
+                dict(waist=-1.0), dict(cells_per_lambda=2)):
+        c = make_config(preset2d("d1", **bad))
+        assert lib.pic2d_workspace_bytes(C.byref(c), C.byref(n)) == N.PIC_EINVAL, bad
+    c = make_config(preset2d("d1"))
+    c.struct_size = C.sizeof(N.Pic2dConfig) - 8
+    assert lib.pic2d_workspace_bytes(C.byref(c), C.byref(n)) == N.PIC_EINVAL
+    assert b"struct_size" in lib.pic_last_error()
+    h = C.c_void_p()
+    c = make_config(preset2d("d1"))
+    assert lib.pic2d_init(C.byref(c), None, 0, None, C.byref(h)) == N.PIC_EINVAL
+    assert lib.pic2d_step(None, 1, None) == N.PIC_EINVAL
+    assert lib.pic2d_diag(None, None, None) == N.PIC_EINVAL
+    assert lib.pic2d_get_state(None, None, None) == N.PIC_EINVAL
+    assert lib.pic2d_timing_enable(None, 1) == N.PIC_EINVAL

@@ -1,0 +1,315 @@
+"""Parity of the 2D3V HIP path (through the C ABI) with the FP64 oracle.
+
+Every input comes from the seeded generators of ``workloads``; every
+expected value comes from ``oracle``.  Tolerances:
+* cell indices, offsets (the move evaluated on the GPU's stored momentum),
+  integer currents and the running integer charge: bit-exact (the 2D
+  deposition contract);
+* one FP32 momentum step: relative error <= 1e-5 of the step's scale
+  max(|u_old|, |u_L|, |u_new|, |dt q E / m|, |RR increment|, 1e-2); FP64 1e-12;
+* one field step: 1e-6 of the field scale (FP32 rounding of the update);
+* whole runs: each energy term within 1e-3 of the injected energy.
+"""
+import numpy as np
+import pytest
+
+from oracle import contract2d, pic2d as opic2d, pusher as opush
+from workloads import preset2d, random_particles2d, random_fields2d
+
+pytestmark = pytest.mark.gpu
+
+F32 = np.float32
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    print(f"\n[gpu] {request.node.name}", flush=True)
+    yield
+    torch.cuda.synchronize()
+
+
+def _run(cfg, capacity=0):
+    from paper_1008_1685_amd.run2d import Run2D
+
+    return Run2D(cfg, capacity=capacity)
+
+
+def _gpu_particles(run, p):
+    return dict(cell=run.encode(p["ix"], p["iy"]), ox=p["ox"], oy=p["oy"], ux=p["ux"], uy=p["uy"],
+                uz=p["uz"], w=p["w"])
+
+
+def _zero_fields(nx, ny):
+    return {k: np.zeros((nx + (2 if k in ("Ex", "By", "Bz") else 1), ny))
+            for k in ("Ex", "Ey", "Ez", "Bx", "By", "Bz")}
+
+
+def _oracle(cfg, fields=None):
+    sim = opic2d.Pic2D(cfg, init_particles=False)
+    for k, v in (fields or {}).items():
+        getattr(sim, k)[:] = v
+    return sim
+
+
+def _setup(cfg, pe, pi, fields, step=0):
+    run = _run(cfg, capacity=max(len(pe["ix"]), len(pi["ix"])))
+    run.set_state({0: _gpu_particles(run, pe), 1: _gpu_particles(run, pi)}, fields=fields, step=step)
+    return run
+
+
+def _contract_currents(cfg, sim, parts, st, run):
+    """Move (from the GPU's stored momenta) and integer currents of the
+    contract; returns the expected (J, new cells, new offsets) per species."""
+    nx, ny = sim.nx, sim.ny
+    J = [np.zeros((nx + 2, ny), np.int64), np.zeros((nx + 3, ny), np.int64),
+         np.zeros((nx + 3, ny), np.int64)]
+    moved = {}
+    for s, p, Z in ((0, parts[0], -1), (1, parts[1], 1)):
+        g = st[f"sp{s}"]
+        ix1, iy1, ox1, oy1, sx, sy, vx, vy, vz, gam = contract2d.move(
+            p["ix"], p["iy"], p["ox"], p["oy"], g["ux"], g["uy"], g["uz"], cfg["cfl"], ny)
+        qw = contract2d.charge_weight(p["w"], sim.w_ref, Z)
+        for k, a in enumerate(contract2d.deposit(p["ix"], p["iy"], p["ox"], p["oy"], sx, sy,
+                                                 ox1, oy1, vz, qw, nx, ny)):
+            J[k] += a
+        moved[s] = (ix1, iy1, ox1, oy1)
+    return J, moved
+
+
+# --------------------------------------------------------------------------- init
+def test_quiet_start_matches_oracle():
+    cfg = preset2d("d1")
+    run = _run(cfg)
+    st = run.get_state()
+    sim = opic2d.Pic2D(cfg)
+    for s in range(2):
+        g = st[f"sp{s}"]
+        ix, iy = run.decode(g["cell"])
+        xi, eta = sim.sp[s]["xi"], sim.sp[s]["eta"]
+        assert np.array_equal(ix, np.floor(xi).astype(np.int64))
+        assert np.array_equal(iy, np.floor(eta).astype(np.int64))
+        assert np.max(np.abs(ix + g["ox"].astype(np.float64) - xi)) < 1e-6
+        assert np.max(np.abs(iy + g["oy"].astype(np.float64) - eta)) < 1e-6
+        assert not np.any(g["ux"]) and np.all(g["w"] == F32(sim.w_ref))
+    d = run.diag()
+    assert d["gauss_int"] == 0 and d["n_alive"] == (sim.sp[0]["xi"].size,) * 2
+    assert not np.any(st["charge_int"])
+
+
+# --------------------------------------------------------------------------- move + deposit
+@pytest.mark.parametrize("n_e,n_i,box_y,ordered,mixed_w", [
+    (40000, 9000, 2.0, True, False),     # dense sorted tiles: LDS box with a row arc
+    (6000, 2000, 0.25, True, False),     # 8 rows: the box wraps every row
+    (3000, 900, 2.0, False, False),      # unsorted: tiles span the grid, global atomics
+    (40000, 9000, 2.0, True, True),      # weights other than the reference weight
+])
+def test_move_and_deposit_bit_exact_without_fields(n_e, n_i, box_y, ordered, mixed_w):
+    # E = B = 0: the push leaves u unchanged, so cells, offsets and currents
+    # must equal the contract evaluated on the inputs
+    cfg = preset2d("d1", box_x=3.0, box_y=box_y, x_foil=1.0)
+    sim = _oracle(cfg)
+    nx, ny = sim.nx, sim.ny
+    pe = random_particles2d(10 + n_e, n_e, 2, nx - 2, ny, sim.w_ref, 1e-3, 1e3, ordered)
+    pi = random_particles2d(11 + n_e, n_i, 2, nx - 2, ny, sim.w_ref, 1e-3, 1e2, ordered)
+    if mixed_w:
+        for p in (pe, pi):
+            f = np.array([1.0, 0.37, 1.0, 1.6, 1.0, 2.9])[np.arange(len(p["w"])) % 6]
+            p["w"] = (p["w"] * f).astype(np.float32).astype(np.float64)
+    run = _setup(cfg, pe, pi, _zero_fields(nx, ny))
+    run.push_deposit()
+    st = run.get_state()
+    for s, p in ((0, pe), (1, pi)):
+        for k in ("ux", "uy", "uz"):
+            assert np.array_equal(st[f"sp{s}"][k], p[k].astype(F32)), k
+    J, moved = _contract_currents(cfg, sim, {0: pe, 1: pi}, st, run)
+    for s in range(2):
+        g = st[f"sp{s}"]
+        ix1, iy1, ox1, oy1 = moved[s]
+        assert np.array_equal(g["cell"], run.encode(ix1, iy1))
+        assert np.array_equal(g["ox"], ox1) and np.array_equal(g["oy"], oy1)
+    assert np.array_equal(st["Jx_int"], J[0])
+    assert np.array_equal(st["Jy_int"], J[1])
+    assert np.array_equal(st["Jz_int"], J[2])
+
+
+# --------------------------------------------------------------------------- full push
+def _push_case(precision, seed, rr=True, n_e=20000, n_i=6000, amp=800.0):
+    cfg = preset2d("d1", box_x=3.0, box_y=2.0, x_foil=1.0, precision=precision, rr=rr)
+    sim = _oracle(cfg)
+    nx, ny = sim.nx, sim.ny
+    f = random_fields2d(seed, nx, ny, amp)
+    pe = random_particles2d(seed + 1, n_e, 2, nx - 2, ny, sim.w_ref, 1e-3, 1e3)
+    pi = random_particles2d(seed + 2, n_i, 2, nx - 2, ny, sim.w_ref, 1e-3, 1e2)
+    run = _setup(cfg, pe, pi, f)
+    run.push_deposit()
+    st = run.get_state()
+    return cfg, _oracle(cfg, f), run, pe, pi, st
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("fp64", 1e-12)])
+@pytest.mark.parametrize("rr", [True, False])
+def test_single_step_push_matches_oracle(precision, tol, rr):
+    cfg, sim, run, pe, pi, st = _push_case(precision, 100, rr=rr)
+    worst = 0.0
+    for s, p in ((0, pe), (1, pi)):
+        g = st[f"sp{s}"]
+        E, B = sim.gather(p["ix"] + p["ox"], p["iy"] + p["oy"])
+        assert np.max(np.abs(B[:, 0])) > 100.0  # B_x takes part
+        u0 = np.stack([p["ux"], p["uy"], p["uz"]], 1)
+        un, uL = opush.push(u0, E, B, sim.qm[s], sim.dt, sim.eps, sim.rr[s])
+        ug = np.stack([g["ux"], g["uy"], g["uz"]], 1).astype(np.float64)
+        if s == 0 and "rx" in g:
+            ug += np.stack([g["rx"], g["ry"], g["rz"]], 1)
+        nrm = lambda a: np.linalg.norm(a, axis=1)
+        scale = np.maximum.reduce([nrm(u0), nrm(uL), nrm(un), abs(sim.qm[s]) * sim.dt * nrm(E),
+                                   nrm(un - uL), np.full(len(u0), 1e-2)])
+        worst = max(worst, float((nrm(ug - un) / scale).max()))
+    assert worst <= tol, worst
+    # cells, offsets and currents follow the contract from the stored momenta
+    J, moved = _contract_currents(cfg, sim, {0: pe, 1: pi}, st, run)
+    for s in range(2):
+        ix1, iy1, ox1, oy1 = moved[s]
+        if precision == "fp32":
+            assert np.array_equal(st[f"sp{s}"]["cell"], run.encode(ix1, iy1))
+            assert np.array_equal(st[f"sp{s}"]["ox"], ox1)
+            assert np.array_equal(st[f"sp{s}"]["oy"], oy1)
+    if precision == "fp32":
+        for k, name in enumerate(("Jx_int", "Jy_int", "Jz_int")):
+            assert np.array_equal(st[name], J[k]), name
+
+
+def test_push_currents_conserve_charge_exactly():
+    # property of the GPU output at any size: charge' - charge + div J = 0
+    cfg, sim, run, pe, pi, st = _push_case("fp32", 200)
+    nx, ny = sim.nx, sim.ny
+    total = np.zeros((nx + 3, ny), np.int64)
+    for s, p, Z in ((0, pe, -1), (1, pi, 1)):
+        g = st[f"sp{s}"]
+        ix, iy = run.decode(g["cell"])
+        total += contract2d.charge(ix, iy, g["ox"], g["oy"], Z * 256, nx, ny)
+        total -= contract2d.charge(p["ix"], p["iy"], p["ox"], p["oy"], Z * 256, nx, ny)
+    assert np.array_equal(total + contract2d.divergence(st["Jx_int"], st["Jy_int"]),
+                          np.zeros_like(total))
+
+
+# --------------------------------------------------------------------------- fields
+@pytest.mark.parametrize("pol,waist", [("LP", 0.6), ("CP", 0.0)])
+def test_field_advance_matches_oracle(pol, waist):
+    cfg = preset2d("d1", box_x=3.0, box_y=1.0, x_foil=1.0, pol=pol, waist=waist, a0=300.0)
+    sim = _oracle(cfg)
+    nx, ny = sim.nx, sim.ny
+    f = random_fields2d(7, nx, ny, 50.0)
+    rng = np.random.default_rng(8)
+    Jx = rng.integers(-2 ** 40, 2 ** 40, size=(nx + 2, ny))
+    Jy = rng.integers(-2 ** 40, 2 ** 40, size=(nx + 3, ny))
+    Jz = rng.integers(-2 ** 40, 2 ** 40, size=(nx + 3, ny))
+    q0 = rng.integers(-2 ** 45, 2 ** 45, size=(nx + 1, ny))
+    step = 200  # mid-pulse
+    run = _run(cfg)
+    empty = dict(ix=np.zeros(0, np.int64), iy=np.zeros(0, np.int64),
+                 **{k: np.zeros(0) for k in ("ox", "oy", "ux", "uy", "uz", "w")})
+    run.set_state({0: _gpu_particles(run, empty), 1: _gpu_particles(run, empty)},
+                  fields=dict(f, Jx_int=Jx, Jy_int=Jy, Jz_int=Jz, charge_int=q0), step=step)
+    run.field_advance()
+    st = run.get_state()
+    sim = _oracle(cfg, f)
+    sim.step_n = step
+    s = sim.w_ref * 2.0 ** -33
+    sim.advance_fields(Jx * s / (sim.dx * sim.dt), Jy * s / (sim.dx * sim.dt),
+                       Jz * s / (sim.dx * sim.dx))
+    assert st["step"] == step + 1
+    for k in ("Ex", "Ey", "Ez", "Bx", "By", "Bz"):
+        ref = getattr(sim, k)
+        d = np.max(np.abs(st[k].astype(np.float64) - ref))
+        assert d <= 1e-6 * max(np.max(np.abs(ref)), 50.0), (k, d)
+    # the running charge took exactly the divergence of the current
+    div = contract2d.divergence(Jx, Jy)[1:nx + 2]
+    assert np.array_equal(st["charge_int"], q0 - div)
+    d = run.diag()
+    for k in ("E_in", "E_out_left", "E_out_right"):
+        assert d[k] == pytest.approx(getattr(sim, k), rel=1e-5, abs=1e-9), k
+    assert not np.any(st["Jx_int"]) and not np.any(st["Jz_int"])  # next buffer cleared
+
+
+# --------------------------------------------------------------------------- sort
+def test_sort_orders_by_cell_and_keeps_every_particle():
+    cfg = preset2d("d1", box_x=3.0, box_y=2.0, x_foil=1.0)
+    sim = _oracle(cfg)
+    nx, ny = sim.nx, sim.ny
+    pe = random_particles2d(21, 50000, 0, nx, ny, sim.w_ref, sort=False)
+    pi = random_particles2d(22, 30000, 0, nx, ny, sim.w_ref, sort=False)
+    run = _setup(cfg, pe, pi, _zero_fields(nx, ny))
+    before = run.get_state()
+    run.sort()
+    st = run.get_state()
+    for s in range(2):
+        a, b = before[f"sp{s}"], st[f"sp{s}"]
+        assert np.all(np.diff(b["cell"]) >= 0)
+        ka = np.lexsort((a["ux"], a["oy"], a["ox"], a["cell"]))
+        kb = np.lexsort((b["ux"], b["oy"], b["ox"], b["cell"]))
+        for k in ("cell", "ox", "oy", "ux", "uy", "uz", "w"):
+            assert np.array_equal(a[k][ka], b[k][kb]), k
+    assert run.diag()["gauss_int"] == 0
+
+
+# --------------------------------------------------------------------------- whole runs
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_laser_foil_run_matches_oracle_budget(precision):
+    cfg = preset2d("d1", precision=precision)
+    sim = opic2d.Pic2D(cfg)
+    steps = 384  # 6 periods: the pulse (3 + 3 periods) reaches the foil at 4
+    run = _run(cfg)
+    run.step(steps)
+    d = run.diag()
+    sim.run(steps)
+    o = sim.diag()
+    assert o["K_e"] > 1e-3 * o["E_in"]  # the foil has been hit
+    for k in ("U_Ex", "U_Et", "U_B", "K_e", "K_i", "E_rad", "E_in", "E_out_left", "E_out_right",
+              "E_esc"):
+        assert abs(d[k] - o[k]) <= 1e-3 * o["E_in"], (k, d[k], o[k])
+    assert abs(d["balance"]) <= 2e-2 * o["E_in"]
+    assert d["gauss_int"] == 0
+    assert d["gauss"] < (1e-3 if precision == "fp32" else 1e-9) * cfg["n0"]
+    assert d["n_alive"] == tuple(sim.sp[s]["xi"].size for s in range(2))
+
+
+# --------------------------------------------------------------------------- full size
+def test_full_size_push_on_samples():
+    # the 2D workload of the benchmark (2,560 x 1,024 cells, 8.4e6 particles)
+    # in the interaction: sampled momenta against the oracle, every cell and
+    # offset against the contract, exact charge continuity over the run
+    cfg = preset2d("d2")
+    run = _run(cfg)
+    run.step(1344)  # 10.5 periods: the pulse is on the foil
+    before = run.get_state()
+    run.push_deposit()
+    after = run.get_state()
+    sim = _oracle(cfg, {k: before[k].astype(np.float64) for k in ("Ex", "Ey", "Ez", "Bx", "By",
+                                                                   "Bz")})
+    rng = np.random.default_rng(5)
+    for s in range(2):
+        a, b = before[f"sp{s}"], after[f"sp{s}"]
+        assert len(a["cell"]) == len(b["cell"])  # nothing left the box
+        ix, iy = run.decode(a["cell"])
+        i1 = run.decode(b["cell"])
+        m = contract2d.move(ix, iy, a["ox"], a["oy"], b["ux"], b["uy"], b["uz"], cfg["cfl"], sim.ny)
+        assert np.array_equal(i1[0], m[0]) and np.array_equal(i1[1], m[1])
+        assert np.array_equal(b["ox"], m[2]) and np.array_equal(b["oy"], m[3])
+        k = rng.choice(len(a["cell"]), 20000, replace=False)
+        E, B = sim.gather(ix[k] + a["ox"][k], iy[k] + a["oy"][k])
+        u0 = np.stack([a["ux"][k], a["uy"][k], a["uz"][k]], 1).astype(np.float64)
+        if s == 0:
+            u0 += np.stack([a["rx"][k], a["ry"][k], a["rz"][k]], 1)
+        un, uL = opush.push(u0, E, B, sim.qm[s], sim.dt, sim.eps, sim.rr[s])
+        ug = np.stack([b["ux"][k], b["uy"][k], b["uz"][k]], 1).astype(np.float64)
+        if s == 0:
+            ug += np.stack([b["rx"][k], b["ry"][k], b["rz"][k]], 1)
+        nrm = lambda v: np.linalg.norm(v, axis=1)
+        scale = np.maximum.reduce([nrm(u0), nrm(uL), nrm(un), abs(sim.qm[s]) * sim.dt * nrm(E),
+                                   nrm(un - uL), np.full(len(k), 1e-2)])
+        assert float((nrm(ug - un) / scale).max()) <= 1e-5
+    run.field_advance()
+    assert run.diag()["gauss_int"] == 0

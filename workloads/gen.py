@@ -95,3 +95,34 @@ def poisson_stream(seed: int = 0, n_runs: int = 256, rate: float = 20.0,
                      rr=True, rr_compensated=True, seed=i, jitter=0.5,
                      periods=float(periods), sort_interval=16, name=f"req{i}")))
     return runs
+
+
+def random_particles2d(seed: int, n: int, ix_lo: int, ix_hi: int, ny: int, w: float,
+                       u_lo=1e-3, u_hi=1e3, sort=True) -> dict:
+    """``n`` particles of a 2D grid: columns [ix_lo, ix_hi), rows [0, ny),
+    uniform in-cell offsets, log-uniform isotropic momenta, weight ``w``;
+    values float32-exact.  sort: ordered by (column, row).  Returned arrays:
+    ix, iy (int64), ox, oy, ux, uy, uz, w (float64 holding float32 values)."""
+    rng = np.random.default_rng(seed)
+    ix = rng.integers(ix_lo, ix_hi, size=n)
+    iy = rng.integers(0, ny, size=n)
+    o = rng.uniform(0.0, 1.0, size=(n, 2)).astype(np.float32)
+    o = np.where(o >= np.float32(1.0), np.float32(0.0), o)
+    mag = np.exp(rng.uniform(np.log(u_lo), np.log(u_hi), size=n))
+    u = (_isotropic(rng, n) * mag[:, None]).astype(np.float32)
+    if sort:
+        order = np.lexsort((iy, ix))
+        ix, iy, o, u = ix[order], iy[order], o[order], u[order]
+    f64 = lambda a: a.astype(np.float64)
+    return dict(ix=ix, iy=iy, ox=f64(o[:, 0]), oy=f64(o[:, 1]), ux=f64(u[:, 0]), uy=f64(u[:, 1]),
+                uz=f64(u[:, 2]), w=f64(np.full(n, np.float32(w), dtype=np.float32)))
+
+
+def random_fields2d(seed: int, nx: int, ny: int, amp: float) -> dict:
+    """Random fields on a 2D Yee grid of nx by ny cells, uniform in [-amp, amp]
+    and float32-exact: node components (Ey, Ez, Bx) have nx + 1 columns,
+    half-node components (Ex, By, Bz) nx + 2; every array has ny rows."""
+    rng = np.random.default_rng(seed)
+    f = lambda m: rng.uniform(-amp, amp, size=(m, ny)).astype(np.float32).astype(np.float64)
+    return dict(Ey=f(nx + 1), Ez=f(nx + 1), Bx=f(nx + 1), Ex=f(nx + 2), By=f(nx + 2),
+                Bz=f(nx + 2))
