@@ -81,6 +81,78 @@ def time_run(cfg, steps, warmup, diag_every, timing=TIMING_PERIOD):
     return out
 
 
+def alg_bytes_per_push_2d(precision: str, compensated: bool, rr: bool):
+    """As alg_bytes_per_push with the second offset: read cell, 2 offsets, 3
+    momenta, weight; write cell, 2 offsets, 3 momenta (+ 24 B of residuals
+    per compensated FP32 electron)."""
+    r = 4 if precision == "fp32" else 8
+    ion = (4 + 6 * r) + (4 + 5 * r)
+    ele = ion + (24 if (precision == "fp32" and compensated and rr) else 0)
+    return ele, ion
+
+
+def time_run_2d(cfg, steps, warmup, timing=TIMING_PERIOD):
+    import torch
+
+    from paper_1008_1685_amd.run2d import Run2D
+
+    run = Run2D(cfg)
+    run.step(warmup)
+    d0 = run.diag()
+    torch.cuda.synchronize()
+    run.timing(timing)
+    t0 = time.perf_counter()
+    run.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = run.timing_read()
+    run.timing(0)
+    d1 = run.diag()
+    out = dict(seconds=t1 - t0, n_e=0.5 * (d0["n_alive"][0] + d1["n_alive"][0]),
+               n_i=0.5 * (d0["n_alive"][1] + d1["n_alive"][1]), kernels=kt, diag1=d1,
+               info=run.get_info())
+    run.close()
+    del run
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_2d(warmup=1280, steps=400):
+    """The 2D3V form (2,560 x 1,024 cells, 8.4e6 particles, LP a0 = 500 with
+    a 4-wavelength waist), timed from the pulse's arrival at the foil: one
+    step = push-deposit, the three field launches, the cell sort every 16
+    steps.  The push kernel's roofline is reported as for the 1D path."""
+    from workloads import preset2d
+
+    cfg = preset2d("d2")
+    r = time_run_2d(cfg, steps, warmup)
+    value = (r["n_e"] + r["n_i"]) * steps / r["seconds"]
+    be, bi = alg_bytes_per_push_2d(cfg["precision"], cfg["rr_compensated"], cfg["rr"])
+    push_ms, push_n = r["kernels"]["push"]
+    avg = push_ms * 1e-3 / max(push_n, 1)
+    nbytes = be * r["n_e"] + bi * r["n_i"]
+    out = dict(workload=f"d2: 2D3V, LP a0={cfg['a0']:g} waist {cfg['waist']:g} wavelengths, "
+                        f"{r['info']['nx']} x {r['info']['ny']} cells, "
+                        f"{int(r['n_e'] + r['n_i'])} particles, fp32 + compensated RR",
+               pushes_per_s=value, ms_per_step=r["seconds"] * 1e3 / steps, steps=steps,
+               warmup=warmup,
+               roofline=dict(bound="hbm", achieved=nbytes / avg / 1e9, peak=PEAK_HBM_GBS, unit="GB/s",
+                             frac=nbytes / avg / 1e9 / PEAK_HBM_GBS, kernel="k_push2",
+                             bytes_per_launch=nbytes, avg_launch_us=avg * 1e6,
+                             alg_bytes_per_push=dict(electron=be, ion=bi)),
+               kernel_us_per_launch={k: v[0] * 1e3 / max(v[1], 1) for k, v in r["kernels"].items()},
+               gauss_int=r["diag1"]["gauss_int"], gauss=r["diag1"]["gauss"],
+               energy_balance=r["diag1"]["balance"] / max(r["diag1"]["E_in"], 1e-300))
+    side = max(steps // 2, 100)
+    r_off = time_run_2d(dict(cfg, rr=False), side, warmup, timing=0)
+    r_64 = time_run_2d(dict(cfg, precision="fp64"), side, warmup, timing=0)
+    v_off = (r_off["n_e"] + r_off["n_i"]) * side / r_off["seconds"]
+    v_64 = (r_64["n_e"] + r_64["n_i"]) * side / r_64["seconds"]
+    out["rr_cost"] = dict(pushes_per_s_rr_off=v_off, overhead=v_off / value - 1.0)
+    out["fp64_path"] = dict(pushes_per_s=v_64, speedup_fp32_over_fp64=value / v_64)
+    return out
+
+
 def side_by_side_c2(warmup=3200, steps=2000):
     """The plain method at scale (12,000 cells, 4e5 particles, LP a0 = 300):
     FP32 and FP64, RR on and off, each timed over the same window at the
@@ -243,6 +315,7 @@ def main():
                     help="only run the stress run with the first N serving requests beside it")
     ap.add_argument("--stress-share", type=float, default=0.2,
                     help="duty cycle of the stress run while requests are served (1: unthrottled)")
+    ap.add_argument("--only-2d", action="store_true", help="only run the 2D3V measurement")
     ap.add_argument("--serve-only", type=int, default=0, metavar="N",
                     help="only run the serving measurement, on the first N requests")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
@@ -265,6 +338,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.serve_only:
         print(json.dumps(dict(serving=serve_bench(n_runs=args.serve_only))), flush=True)
+        return
+    if args.only_2d:
+        print(json.dumps(dict(pic2d=bench_2d())), flush=True)
         return
     if args.stress_only:
         print(json.dumps(dict(stress=stress_bench(dict(n_runs=args.stress_only), share=args.stress_share))),
@@ -325,6 +401,7 @@ def main():
                                paper="about +10% compute time with RR (Section 3)")
         line["fp64_path"] = dict(pushes_per_s=v_64, speedup_fp32_over_fp64=value / v_64)
         line["plain_method_scale"] = side_by_side_c2()
+        line["pic2d"] = bench_2d()
         line["cpu_baseline"] = cpu_baseline(cfg)
     if not args.no_serve:
         line["serving"] = serve_bench()

@@ -1083,57 +1083,63 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
   return v + (row >= 1 ? r0 : 0) + (row >= 2 ? r1 : 0) + (row >= 3 ? r2 : 0);
 }
 
-// exclusive scan of the per-cell counts of one species (one work-group of
-// 1024 threads); the alive count goes to *new_count (the count slot of the
-// destination arrays) and the counts are cleared for the next histogram.
-// Chunks of 8192 cells pass through LDS so that every global access is
-// coalesced; within a chunk thread t scans cells 8t .. 8t + 7.
+// Exclusive scan of one chunk of kScanChunk per-cell counts (one work-group
+// of 1024 threads), starting from `carry`: the chunk passes through LDS so
+// that every global access is coalesced; within it thread t scans cells
+// 8t .. 8t + 7.  Writes the cursors, clears the counts for the next
+// histogram and returns the chunk's total.
 constexpr int kScanThreads = 1024, kScanPer = 8, kScanChunk = kScanThreads * kScanPer;
+__device__ __forceinline__ int scan_chunk(int* cnt, int* cur, int c0, int nx, long long carry,
+                                          int* stage, int* wsum) {
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    const int j = c0 + k * kScanThreads + t;
+    stage[k * kScanThreads + t] = j < nx ? cnt[j] : 0;
+  }
+  __syncthreads();
+  int v[kScanPer], sum = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    v[k] = stage[t * kScanPer + k];
+    sum += v[k];
+  }
+  const int incl = wave_incl_scan(sum);
+  if (lane == 63) wsum[wid] = incl;
+  __syncthreads();
+  int before = 0, total = 0;
+  for (int w = 0; w < kScanThreads / kLanes; ++w) {
+    before += w < wid ? wsum[w] : 0;
+    total += wsum[w];
+  }
+  int run = (int)carry + before + incl - sum;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    stage[t * kScanPer + k] = run;
+    run += v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    const int j = c0 + k * kScanThreads + t;
+    if (j < nx) {
+      cur[j] = stage[k * kScanThreads + t];
+      cnt[j] = 0;
+    }
+  }
+  __syncthreads();  // stage and wsum are reused by the next chunk
+  return total;
+}
+
+// exclusive scan of the per-cell counts of one species in one work-group,
+// chunk after chunk; the alive count goes to *new_count (the count slot of
+// the destination arrays)
 __device__ __forceinline__ void sort_scan_species(int* cnt, int* cur, long long* new_count, int nx) {
   __shared__ int stage[kScanChunk];
   __shared__ int wsum[kScanThreads / kLanes];
-  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
   long long carry = 0;
-  for (int c0 = 0; c0 < nx; c0 += kScanChunk) {
-#pragma unroll
-    for (int k = 0; k < kScanPer; ++k) {
-      const int j = c0 + k * kScanThreads + t;
-      stage[k * kScanThreads + t] = j < nx ? cnt[j] : 0;
-    }
-    __syncthreads();
-    int v[kScanPer], sum = 0;
-#pragma unroll
-    for (int k = 0; k < kScanPer; ++k) {
-      v[k] = stage[t * kScanPer + k];
-      sum += v[k];
-    }
-    const int incl = wave_incl_scan(sum);
-    if (lane == 63) wsum[wid] = incl;
-    __syncthreads();
-    int before = 0, total = 0;
-    for (int w = 0; w < kScanThreads / kLanes; ++w) {
-      before += w < wid ? wsum[w] : 0;
-      total += wsum[w];
-    }
-    int run = (int)carry + before + incl - sum;
-#pragma unroll
-    for (int k = 0; k < kScanPer; ++k) {
-      stage[t * kScanPer + k] = run;
-      run += v[k];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < kScanPer; ++k) {
-      const int j = c0 + k * kScanThreads + t;
-      if (j < nx) {
-        cur[j] = stage[k * kScanThreads + t];
-        cnt[j] = 0;
-      }
-    }
-    carry += total;
-    __syncthreads();  // stage and wsum are reused by the next chunk
-  }
-  if (t == 0) *new_count = carry;
+  for (int c0 = 0; c0 < nx; c0 += kScanChunk) carry += scan_chunk(cnt, cur, c0, nx, carry, stage, wsum);
+  if (threadIdx.x == 0) *new_count = carry;
 }
 
 __global__ __launch_bounds__(1024) void k_sort_scan(int* cnt0, int* cnt1, int* cur0, int* cur1,

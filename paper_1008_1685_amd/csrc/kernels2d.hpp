@@ -7,11 +7,10 @@
 // Kernels:
 //   k_push2     gather -> Boris -> RR (electrons) -> 2D move -> fixed-point
 //               Esirkepov deposit, one thread per particle over cell-sorted
-//               tiles.  A particle's 40 current terms (its old cell's 4 x 4
-//               node stencil) are summed over the lanes of each 16-lane row
-//               that share the old cell (DPP row shifts); the row's last
-//               lane adds the sums to an LDS box of the tile's cells, which
-//               goes to HBM with one 64-bit atomic per node at the end.
+//               tiles.  Each lane adds the non-zero terms of its particle's
+//               3 x 3 stencil to one of several private copies of an LDS box
+//               covering the tile's cells; the box goes to HBM with one
+//               64-bit atomic per node at the end.
 //   k_field2_b  half step of B (run before and after the E step).
 //   k_field2_e  E step, boundary guards, Poynting bookkeeping, the running
 //               integer charge implied by the current, and the clearing of
@@ -42,9 +41,10 @@ constexpr int k2One = 1 << k2Q;
 constexpr int k2PPT = PIC2D_PUSH_PPT;     // particles per thread per tile
 constexpr int k2Tile = kThreads * k2PPT;
 constexpr int k2Slots = PIC2D_LDS_SLOTS;  // 64-bit LDS accumulators per work-group
-constexpr int k2Cols = 8;                 // columns of the LDS box (x)
-constexpr int k2MaxRows = k2Slots / (3 * k2Cols);
-constexpr int k2Terms = 40;               // 12 Jx + 12 Jy + 16 Jz terms per particle
+#ifndef PIC2D_MAX_COPIES
+#define PIC2D_MAX_COPIES 8
+#endif
+constexpr int k2MaxCopies = PIC2D_MAX_COPIES;  // private LDS copies per current slot, at most
 
 // staggered field pairs: (E_y, B_x) at (node, half-row), (E_x, B_y) at (half-node, row)
 template <typename R>
@@ -187,138 +187,110 @@ __device__ __forceinline__ void contract_move2(R ux, R uy, R uz, R ox, R oy, R c
   sy = fl;
 }
 
-// 12-bit weights of one direction on the nodes (old cell - 1) .. (old cell + 2)
+// 12-bit weights of one direction on the three nodes base .. base + 2,
+// base = min(old cell, new cell): the old cell sits at base + d0, the new
+// one at base + d1 (d0, d1 in {0, 1})
 template <typename R>
-__device__ __forceinline__ void shapes2(R o, R o1, int sh, int (&S0)[4], int (&S1)[4]) {
+__device__ __forceinline__ void shapes2(R o, R o1, int sh, int (&S0)[3], int (&S1)[3]) {
   const int q0 = (int)(o * R(k2One)), q1 = (int)(o1 * R(k2One));
-  S0[0] = 0;
-  S0[1] = k2One - q0;
-  S0[2] = q0;
-  S0[3] = 0;
-  S1[0] = sh < 0 ? k2One - q1 : 0;
-  S1[1] = sh == 0 ? k2One - q1 : (sh < 0 ? q1 : 0);
-  S1[2] = sh > 0 ? k2One - q1 : (sh == 0 ? q1 : 0);
-  S1[3] = sh > 0 ? q1 : 0;
+  const bool d0 = sh < 0, d1 = sh > 0;
+  S0[0] = d0 ? 0 : k2One - q0;
+  S0[1] = d0 ? k2One - q0 : q0;
+  S0[2] = d0 ? q0 : 0;
+  S1[0] = d1 ? 0 : k2One - q1;
+  S1[1] = d1 ? k2One - q1 : q1;
+  S1[2] = d1 ? q1 : 0;
 }
 
-// The fixed-point Esirkepov terms of one move (see the 2D deposition
-// contract): t[a * 4 + b] Jx on face a + 1/2 (a < 3) and row b,
-// t[12 + a * 3 + b] Jy on node a and half-row b + 1/2 (b < 3),
-// t[24 + a * 4 + b] Jz on node a and row b; a, b count from (old cell - 1).
-// Every term is below 2^25, so 24-bit multiplies are exact.
-template <typename R>
-__device__ __forceinline__ void deposit2_terms(R ox, R oy, R ox1, R oy1, int sx, int sy, R vz,
-                                               int (&t)[k2Terms]) {
-  int X0[4], X1[4], Y0[4], Y1[4];
-  shapes2<R>(ox, ox1, sx, X0, X1);
-  shapes2<R>(oy, oy1, sy, Y0, Y1);
-  int Cx[3], Cy[3];
-  Cx[0] = X0[0] - X1[0];
-  Cy[0] = Y0[0] - Y1[0];
-#pragma unroll
-  for (int a = 1; a < 3; ++a) {
-    Cx[a] = Cx[a - 1] + (X0[a] - X1[a]);
-    Cy[a] = Cy[a - 1] + (Y0[a] - Y1[a]);
-  }
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) t[a * 4 + b] = __mul24(Cx[a], Y0[b] + Y1[b]);
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) t[12 + a * 3 + b] = __mul24(X0[a] + X1[a], Cy[b]);
-  const int vz12 = (int)rint(vz * R(k2One));
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-      t[24 + a * 4 + b] = __mul24(vz12, (__mul24(X0[a], Y0[b]) + __mul24(X1[a], Y1[b])) >> k2Q);
-}
-
-// LDS current box of one tile: columns xmn .. xmn + 7 (Jx: half-nodes
-// h = xmn + c; Jy, Jz: node index xmn + c, i.e. node xmn - 1 + c), rows
-// jbase .. jbase + BY - 1 (mod ny); slot (comp, r, c) at comp * 8 BY + 8 r + c
+// LDS current box of one tile: BX columns from xmn (Jx: half-node
+// h = xmn + c; Jy, Jz: node index xmn + c, i.e. node xmn - 1 + c) and BY
+// rows from jbase (mod ny), NC private copies per slot (lane & (NC - 1)
+// picks one, so that lanes of a wave in one cell add to different words):
+// copy k of slot (comp, r, c) at ((comp BY + r) BX + c) NC + k
 struct Box2 {
   unsigned long long* lds;
-  int xmn, jbase, BY;
+  int xmn, jbase, BX, BY, NC, copy;
   bool use;
 };
 
-// inclusive scan over the 16 lanes of each row; lane 15 of a row ends with
-// the row's sum (all lanes of the wave active)
-__device__ __forceinline__ int row_sum16(int v) {
-  v += row_shr<1>(0, v);
-  v += row_shr<2>(0, v);
-  v += row_shr<4>(0, v);
-  v += row_shr<8>(0, v);
-  return v;
-}
-
-// Deposit the terms of the wave's particles.  Lanes with the reference
-// charge weight are grouped by old cell: per pass, each 16-lane row takes
-// the cell of its first pending lane, sums the terms of its lanes in that
-// cell, and its last lane adds the 40 sums to the box (or to HBM when the
-// tile has no box); passes repeat until every lane is done.  Other weights
-// (none in uniform-weight runs) add their own terms to HBM.
+// The fixed-point Esirkepov current of one move (the 2D deposition
+// contract), added term by term to the box (or to HBM when the tile has no
+// box).  With base = min(old, new) cell in each direction and 3-node weights
+// S0 (old), S1 (new): C[a] = sum_{a' <= a} (S0 - S1)[a'], Sig = S0 + S1,
+//   Jx(face base + a + 1/2, row b) += qw C_x[a] Sig_y[b]      a < 2, b < 3
+//   Jy(node a, half-row base + b + 1/2) += qw Sig_x[a] C_y[b]  a < 3, b < 2
+//   Jz(node a, row b) += qw rint(v_z 2^12) ((S0_x S0_y + S1_x S1_y)[a, b] >> 12).
+// Terms that vanish for a move without a cell change in x (face 1, node 2)
+// or y (row 2, half-row 1) are not added.  Every term is below 2^25, so the
+// 24-bit multiplies are exact.  Terms of particles with the reference weight
+// go to the box as multiples of it.
 template <typename R>
-__device__ __forceinline__ void deposit2_wave(const Push2Args<R>& a, const Box2& bx, int cell,
-                                              bool dep, int qw, int qw_ref, const int (&t)[k2Terms]) {
-  const int lane = threadIdx.x & 63, row = lane >> 4;
-  const int ymask = (1 << a.ysh) - 1, ny = a.ny;
-  unsigned long long act = __ballot(dep && qw == qw_ref);
-  while (act) {
-    int Lr[4];
+__device__ __forceinline__ void deposit2(const Push2Args<R>& a, const Box2& bx, int ix, int iy, R ox,
+                                         R oy, R ox1, R oy1, int sx, int sy, R vz, int qw, int qw_ref) {
+  int X0[3], X1[3], Y0[3], Y1[3];
+  shapes2<R>(ox, ox1, sx, X0, X1);
+  shapes2<R>(oy, oy1, sy, Y0, Y1);
+  const int Cx0 = X0[0] - X1[0], Cx1 = Cx0 + (X0[1] - X1[1]);
+  const int Cy0 = Y0[0] - Y1[0], Cy1 = Cy0 + (Y0[1] - Y1[1]);
+  const int vz12 = (int)rint(vz * R(k2One));
+  const bool mx = sx != 0, my = sy != 0;
+  const int ny = a.ny;
+  const int bxn = min(ix, ix + sx) + 1;  // column index of node base (guard offset 1)
+  const int by0 = min(iy, iy + sy);      // base row, -1 .. ny - 1 before wrapping
+  const bool box = bx.use && qw == qw_ref;
+  const long long mul = box ? 1ll : (long long)qw;
+  int rb[3];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const unsigned m = (unsigned)(act >> (16 * r)) & 0xffffu;
-      Lr[r] = m ? __builtin_amdgcn_readlane(cell, 16 * r + __builtin_ctz(m)) : kDead;
-    }
-    const int myL = row == 0 ? Lr[0] : (row == 1 ? Lr[1] : (row == 2 ? Lr[2] : Lr[3]));
-    const bool mine = ((act >> lane) & 1ull) && cell == myL;
-    const bool writer = (lane & 15) == 15 && myL != kDead;
-    // addresses of the writer lanes: row offsets of the leader cell's stencil
-    const int lx = myL >> a.ysh, ly = myL & ymask;
-    int rb[4];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      int r = ly - 1 + b - (bx.use ? bx.jbase : 0);
-      r += r < 0 ? ny : 0;
-      r -= r >= ny ? ny : 0;
-      rb[b] = r;
-    }
-    const int c0 = lx - bx.xmn;
-#pragma unroll
-    for (int q = 0; q < k2Terms; ++q) {
-      const int v = row_sum16(mine ? t[q] : 0);
-      // (comp, column offset a, row b) of term q
-      const int comp = q < 12 ? 0 : (q < 24 ? 1 : 2);
-      const int ca = q < 12 ? q / 4 : (q < 24 ? (q - 12) / 3 : (q - 24) / 4);
-      const int rbq = q < 12 ? q % 4 : (q < 24 ? (q - 12) % 3 : (q - 24) % 4);
-      if (writer) {
-        if (bx.use) {
-          atomicAdd(bx.lds + comp * 8 * bx.BY + rb[rbq] * 8 + c0 + ca,
-                    (unsigned long long)(long long)v);
-        } else {
-          atomicAdd(a.J[comp] + (size_t)(lx + ca) * ny + rb[rbq],
-                    (unsigned long long)((long long)v * qw_ref));
-        }
-      }
-    }
-    act &= ~__ballot(mine);
+  for (int b = 0; b < 3; ++b) {
+    int r = by0 + b - (box ? bx.jbase : 0);
+    r += r < 0 ? ny : 0;
+    r -= r >= ny ? ny : 0;
+    rb[b] = r;
   }
-  if (dep && qw != qw_ref) {
-    const int lx = cell >> a.ysh, ly = cell & ymask;
-#pragma unroll
-    for (int q = 0; q < k2Terms; ++q) {
-      const int comp = q < 12 ? 0 : (q < 24 ? 1 : 2);
-      const int ca = q < 12 ? q / 4 : (q < 24 ? (q - 12) / 3 : (q - 24) / 4);
-      const int rbq = q < 12 ? q % 4 : (q < 24 ? (q - 12) % 3 : (q - 24) % 4);
-      int r = ly - 1 + rbq;
-      r += r < 0 ? ny : 0;
-      r -= r >= ny ? ny : 0;
-      atomicAdd(a.J[comp] + (size_t)(lx + ca) * ny + r, (unsigned long long)((long long)t[q] * qw));
-    }
+  const int c0 = bxn - (box ? bx.xmn : 0);
+  auto add = [&](int comp, int ca, int b, int v) {
+    if (box)
+      atomicAdd(bx.lds + ((size_t)((comp * bx.BY + rb[b]) * bx.BX + c0 + ca) * bx.NC + bx.copy),
+                (unsigned long long)(long long)v);
+    else
+      atomicAdd(a.J[comp] + (size_t)(c0 + ca) * ny + rb[b], (unsigned long long)((long long)v * mul));
+  };
+  const int Sy0 = Y0[0] + Y1[0], Sy1 = Y0[1] + Y1[1], Sy2 = Y0[2] + Y1[2];
+  const int Sx0 = X0[0] + X1[0], Sx1 = X0[1] + X1[1], Sx2 = X0[2] + X1[2];
+  // Jx
+  add(0, 0, 0, __mul24(Cx0, Sy0));
+  add(0, 0, 1, __mul24(Cx0, Sy1));
+  if (my) add(0, 0, 2, __mul24(Cx0, Sy2));
+  if (mx) {
+    add(0, 1, 0, __mul24(Cx1, Sy0));
+    add(0, 1, 1, __mul24(Cx1, Sy1));
+    if (my) add(0, 1, 2, __mul24(Cx1, Sy2));
+  }
+  // Jy
+  add(1, 0, 0, __mul24(Sx0, Cy0));
+  add(1, 1, 0, __mul24(Sx1, Cy0));
+  if (mx) add(1, 2, 0, __mul24(Sx2, Cy0));
+  if (my) {
+    add(1, 0, 1, __mul24(Sx0, Cy1));
+    add(1, 1, 1, __mul24(Sx1, Cy1));
+    if (mx) add(1, 2, 1, __mul24(Sx2, Cy1));
+  }
+  // Jz
+  auto tz = [&](int i, int j) {
+    return __mul24(vz12, (__mul24(X0[i], Y0[j]) + __mul24(X1[i], Y1[j])) >> k2Q);
+  };
+  add(2, 0, 0, tz(0, 0));
+  add(2, 1, 0, tz(1, 0));
+  add(2, 0, 1, tz(0, 1));
+  add(2, 1, 1, tz(1, 1));
+  if (mx) {
+    add(2, 2, 0, tz(2, 0));
+    add(2, 2, 1, tz(2, 1));
+  }
+  if (my) {
+    add(2, 0, 2, tz(0, 2));
+    add(2, 1, 2, tz(1, 2));
+    if (mx) add(2, 2, 2, tz(2, 2));
   }
 }
 
@@ -330,12 +302,8 @@ struct Acc2 {
 // terms (zero and dep = false for removed particles).
 template <typename R, bool RR, bool COMP>
 __device__ __forceinline__ void push2_particle(const Push2Args<R>& a, const SpeciesDev<R>& sp, int s,
-                                               unsigned ui, const P2<R>& pd, int (&t)[k2Terms],
-                                               int& qw, bool& dep, Acc2& acc) {
-  dep = false;
-  qw = 0;
-#pragma unroll
-  for (int q = 0; q < k2Terms; ++q) t[q] = 0;
+                                               unsigned ui, const P2<R>& pd, const Box2& box,
+                                               Acc2& acc) {
   if (pd.c == kDead) return;
   const int ymask = (1 << a.ysh) - 1;
   const int ix = pd.c >> a.ysh, iy = pd.c & ymask;
@@ -354,9 +322,8 @@ __device__ __forceinline__ void push2_particle(const Push2Args<R>& a, const Spec
     return;
   }
   const int sx = (int)shx, sy = (int)shy;
-  qw = a.Z[s] * (int)rint(pd.w * a.sw);
-  dep = true;
-  deposit2_terms<R>(pd.ox, pd.oy, ox1, oy1, sx, sy, vz, t);
+  const int qw = a.Z[s] * (int)rint(pd.w * a.sw);
+  deposit2<R>(a, box, ix, iy, pd.ox, pd.oy, ox1, oy1, sx, sy, vz, qw, a.qw_ref[s]);
   if (RR) {
     const R num = mo.ddx * (R(2) * mo.Lx + mo.ddx) + mo.ddy * (R(2) * mo.Ly + mo.ddy) +
                   mo.ddz * (R(2) * mo.Lz + mo.ddz);
@@ -443,39 +410,41 @@ __device__ __forceinline__ void push2_tile(const Push2Args<R>& a, int s, int til
   dmx = max(max(s_red[3][0], s_red[3][1]), max(s_red[3][2], s_red[3][3]));
   if (xmn > xmx) return;  // every particle of the tile was removed (block-uniform)
 
+  // box: columns xmn - 1 .. xmx + 2, rows of the arc plus one below and two
+  // above (or every row, the stencils wrapping onto it)
   Box2 bx;
   bx.lds = lds;
   bx.xmn = xmn;
-  bx.use = xmx - xmn <= k2Cols - 4;
-  const int span = dmx - dmn + 4;  // rows of the stencils: arc plus one below and two above
-  if (span < ny && span <= k2MaxRows) {
+  bx.BX = xmx - xmn + 4;
+  const int span = dmx - dmn + 4;
+  if (span < ny) {
     bx.BY = span;
     int jb = jref + dmn - 1;
     jb += jb < 0 ? ny : 0;
     jb -= jb >= ny ? ny : 0;
     bx.jbase = jb;
   } else {
-    bx.BY = ny;  // every row: stencil rows wrap onto the box
+    bx.BY = ny;
     bx.jbase = 0;
-    bx.use = bx.use && ny <= k2MaxRows;
   }
-  const int E = 3 * k2Cols * bx.BY;
+  const int slots = 3 * bx.BX * bx.BY;
+  int nc = k2MaxCopies;
+  while (nc > 1 && slots * nc > k2Slots) nc >>= 1;
+  bx.NC = nc;
+  bx.copy = lane & (nc - 1);
+  bx.use = slots * nc <= k2Slots;
   if (bx.use)
-    for (int e = tid; e < E; e += kThreads) lds[e] = 0ull;
+    for (int e = tid; e < slots * nc; e += kThreads) lds[e] = 0ull;
   __syncthreads();
 
   Acc2 acc{0.f, 0.f, 0.f};
-  const int qw_ref = a.qw_ref[s];
   P2<R> cur = load2<R, COMP>(sp, base + tid, n, cl[0]);
 #pragma unroll 2
   for (int k = 0; k < k2PPT; ++k) {
     const int i = base + k * kThreads + tid;
     P2<R> nxt;
     if (k + 1 < k2PPT) nxt = load2<R, COMP>(sp, i + kThreads, n, cl[k + 1]);
-    int t[k2Terms], qw;
-    bool dep;
-    push2_particle<R, RR, COMP>(a, sp, s, (unsigned)i, cur, t, qw, dep, acc);
-    deposit2_wave<R>(a, bx, cur.c, dep, qw, qw_ref, t);
+    push2_particle<R, RR, COMP>(a, sp, s, (unsigned)i, cur, bx, acc);
     if (k + 1 < k2PPT) cur = nxt;
   }
 
@@ -488,13 +457,15 @@ __device__ __forceinline__ void push2_tile(const Push2Args<R>& a, int s, int til
   }
   __syncthreads();
   if (bx.use) {
-    const int BY8 = 8 * bx.BY;
-    for (int e = tid; e < E; e += kThreads) {
-      const long long v = (long long)lds[e];
+    const int P = bx.BX * bx.BY;
+    const long long qw_ref = a.qw_ref[s];
+    for (int e = tid; e < slots; e += kThreads) {
+      long long v = 0;
+      for (int k = 0; k < bx.NC; ++k) v += (long long)lds[e * bx.NC + k];
       if (v) {
-        const int comp = e >= 2 * BY8 ? 2 : (e >= BY8 ? 1 : 0);
-        const int rem = e - comp * BY8;
-        const int r = rem >> 3, c = rem & 7;
+        const int comp = e >= 2 * P ? 2 : (e >= P ? 1 : 0);
+        const int rem = e - comp * P;
+        const int r = rem / bx.BX, c = rem - r * bx.BX;
         int gy = bx.jbase + r;
         gy -= gy >= ny ? ny : 0;
         atomicAdd(a.J[comp] + (size_t)(xmn + c) * ny + gy, (unsigned long long)(v * qw_ref));
@@ -533,6 +504,41 @@ __global__ __launch_bounds__(kThreads) void k_push2(Push2Args<R> a) {
   } else {
     push2_tile<R, false, false>(a, s, tile, n, base, lds);
   }
+}
+
+// Exclusive scan of the cell counts of a 2D grid (millions of keys): the
+// chunks of both species in parallel, then each chunk adds the totals of the
+// chunks before it; the last chunk writes the alive count.
+__global__ __launch_bounds__(kScanThreads) void k_scan2_chunks(int* cnt0, int* cnt1, int* cur0,
+                                                              int* cur1, int* tot, int nkeys,
+                                                              int nchunks) {
+  __shared__ int stage[kScanChunk];
+  __shared__ int wsum[kScanThreads / kLanes];
+  const int s = blockIdx.y, c = blockIdx.x;
+  const int t = scan_chunk(s ? cnt1 : cnt0, s ? cur1 : cur0, c * kScanChunk, nkeys, 0, stage, wsum);
+  if (threadIdx.x == 0) tot[s * nchunks + c] = t;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan2_offsets(int* cur0, int* cur1, const int* tot,
+                                                               long long* new_count, int nkeys,
+                                                               int nchunks) {
+  __shared__ long long red[kScanThreads / kLanes];
+  const int s = blockIdx.y, c = blockIdx.x, t = threadIdx.x;
+  const int* T = tot + s * nchunks;
+  long long v = 0;
+  for (int k = t; k < c; k += kScanThreads) v += T[k];
+  v = wave_sum(v);
+  if ((t & 63) == 0) red[t >> 6] = v;
+  __syncthreads();
+  long long off = 0;
+  for (int w = 0; w < kScanThreads / kLanes; ++w) off += red[w];
+  int* cur = s ? cur1 : cur0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    const int j = c * kScanChunk + k * kScanThreads + t;
+    if (j < nkeys) cur[j] += (int)off;
+  }
+  if (c == nchunks - 1 && t == 0) new_count[s] = off + T[c];
 }
 
 // cell sort of 2D particles: the 1D passes, with the y offset moved too

@@ -100,20 +100,34 @@ def test_quiet_start_matches_oracle():
 
 
 # --------------------------------------------------------------------------- move + deposit
-@pytest.mark.parametrize("n_e,n_i,box_y,ordered,mixed_w", [
-    (40000, 9000, 2.0, True, False),     # dense sorted tiles: LDS box with a row arc
-    (6000, 2000, 0.25, True, False),     # 8 rows: the box wraps every row
-    (3000, 900, 2.0, False, False),      # unsorted: tiles span the grid, global atomics
-    (40000, 9000, 2.0, True, True),      # weights other than the reference weight
+def _shuffle_within(p, block, seed):
+    """Particles in random order inside consecutive blocks (one push tile
+    each): tiles stay compact, the lanes of a wave see many cells."""
+    rng = np.random.default_rng(seed)
+    n = len(p["ix"])
+    order = np.concatenate([b0 + rng.permutation(min(block, n - b0)) for b0 in range(0, n, block)])
+    return {k: v[order] for k, v in p.items()}
+
+
+@pytest.mark.parametrize("n_e,n_i,box_y,order,mixed_w", [
+    (40000, 9000, 2.0, "sorted", False),     # dense sorted tiles: row groups into an LDS box
+    (6000, 2000, 0.25, "sorted", False),     # 8 rows: the box wraps every row
+    (40000, 9000, 2.0, "tiles", False),      # compact tiles, spread waves: per-lane LDS adds
+    (3000, 900, 2.0, "none", False),         # unsorted: tiles span the grid, HBM atomics
+    (40000, 9000, 2.0, "sorted", True),      # weights other than the reference weight
 ])
-def test_move_and_deposit_bit_exact_without_fields(n_e, n_i, box_y, ordered, mixed_w):
+def test_move_and_deposit_bit_exact_without_fields(n_e, n_i, box_y, order, mixed_w):
     # E = B = 0: the push leaves u unchanged, so cells, offsets and currents
     # must equal the contract evaluated on the inputs
     cfg = preset2d("d1", box_x=3.0, box_y=box_y, x_foil=1.0)
     sim = _oracle(cfg)
     nx, ny = sim.nx, sim.ny
+    ordered = order != "none"
     pe = random_particles2d(10 + n_e, n_e, 2, nx - 2, ny, sim.w_ref, 1e-3, 1e3, ordered)
     pi = random_particles2d(11 + n_e, n_i, 2, nx - 2, ny, sim.w_ref, 1e-3, 1e2, ordered)
+    if order == "tiles":
+        tile = _run(cfg).info["tile"]
+        pe, pi = _shuffle_within(pe, tile, 1), _shuffle_within(pi, tile, 2)
     if mixed_w:
         for p in (pe, pi):
             f = np.array([1.0, 0.37, 1.0, 1.6, 1.0, 2.9])[np.arange(len(p["w"])) % 6]
