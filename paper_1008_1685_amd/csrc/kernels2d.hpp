@@ -204,12 +204,14 @@ __device__ __forceinline__ void shapes2(R o, R o1, int sh, int (&S0)[3], int (&S
 
 // LDS current box of one tile: BX columns from xmn (Jx: half-node
 // h = xmn + c; Jy, Jz: node index xmn + c, i.e. node xmn - 1 + c) and BY
-// rows from jbase (mod ny), NC private copies per slot (lane & (NC - 1)
-// picks one, so that lanes of a wave in one cell add to different words):
-// copy k of slot (comp, r, c) at ((comp BY + r) BX + c) NC + k
+// rows from jbase (mod ny); slot (comp, r, c) = (comp BY + r) BX + c.  NC
+// private copies of the whole box, CS words apart (CS odd, so that the same
+// slot of different copies falls in different banks); lane & (NC - 1)
+// picks the copy, so that lanes of a wave in one cell add to different words
 struct Box2 {
   unsigned long long* lds;
-  int xmn, jbase, BX, BY, NC, copy;
+  int xmn, jbase, BX, BY, NC, CS;
+  int copy;                  // offset of this lane's copy
   bool use;
 };
 
@@ -224,73 +226,99 @@ struct Box2 {
 // or y (row 2, half-row 1) are not added.  Every term is below 2^25, so the
 // 24-bit multiplies are exact.  Terms of particles with the reference weight
 // go to the box as multiples of it.
+struct Terms2 {
+  int X0[3], X1[3], Y0[3], Y1[3], Cx[2], Cy[2], vz12;
+  bool mx, my;
+  __device__ __forceinline__ int jx(int i, int j) const { return __mul24(Cx[i], Y0[j] + Y1[j]); }
+  __device__ __forceinline__ int jy(int i, int j) const { return __mul24(X0[i] + X1[i], Cy[j]); }
+  __device__ __forceinline__ int jz(int i, int j) const {
+    return __mul24(vz12, (__mul24(X0[i], Y0[j]) + __mul24(X1[i], Y1[j])) >> k2Q);
+  }
+};
+
+template <typename R>
+__device__ __forceinline__ Terms2 terms2(R ox, R oy, R ox1, R oy1, int sx, int sy, R vz) {
+  Terms2 t;
+  shapes2<R>(ox, ox1, sx, t.X0, t.X1);
+  shapes2<R>(oy, oy1, sy, t.Y0, t.Y1);
+  t.Cx[0] = t.X0[0] - t.X1[0];
+  t.Cx[1] = t.Cx[0] + (t.X0[1] - t.X1[1]);
+  t.Cy[0] = t.Y0[0] - t.Y1[0];
+  t.Cy[1] = t.Cy[0] + (t.Y0[1] - t.Y1[1]);
+  t.vz12 = (int)rint(vz * R(k2One));
+  t.mx = sx != 0;
+  t.my = sy != 0;
+  return t;
+}
+
+// add the terms through `put(comp, column offset, row b, value)` (columns
+// and rows counted from the stencil base)
+template <typename Put>
+__device__ __forceinline__ void add_terms2(const Terms2& t, Put&& put) {
+  put(0, 0, 0, t.jx(0, 0));
+  put(0, 0, 1, t.jx(0, 1));
+  put(1, 0, 0, t.jy(0, 0));
+  put(1, 1, 0, t.jy(1, 0));
+  put(2, 0, 0, t.jz(0, 0));
+  put(2, 1, 0, t.jz(1, 0));
+  put(2, 0, 1, t.jz(0, 1));
+  put(2, 1, 1, t.jz(1, 1));
+  if (t.mx) {
+    put(0, 1, 0, t.jx(1, 0));
+    put(0, 1, 1, t.jx(1, 1));
+    put(1, 2, 0, t.jy(2, 0));
+    put(2, 2, 0, t.jz(2, 0));
+    put(2, 2, 1, t.jz(2, 1));
+  }
+  if (t.my) {
+    put(0, 0, 2, t.jx(0, 2));
+    put(1, 0, 1, t.jy(0, 1));
+    put(1, 1, 1, t.jy(1, 1));
+    put(2, 0, 2, t.jz(0, 2));
+    put(2, 1, 2, t.jz(1, 2));
+    if (t.mx) {
+      put(0, 1, 2, t.jx(1, 2));
+      put(1, 2, 1, t.jy(2, 1));
+      put(2, 2, 2, t.jz(2, 2));
+    }
+  }
+}
+
 template <typename R>
 __device__ __forceinline__ void deposit2(const Push2Args<R>& a, const Box2& bx, int ix, int iy, R ox,
                                          R oy, R ox1, R oy1, int sx, int sy, R vz, int qw, int qw_ref) {
-  int X0[3], X1[3], Y0[3], Y1[3];
-  shapes2<R>(ox, ox1, sx, X0, X1);
-  shapes2<R>(oy, oy1, sy, Y0, Y1);
-  const int Cx0 = X0[0] - X1[0], Cx1 = Cx0 + (X0[1] - X1[1]);
-  const int Cy0 = Y0[0] - Y1[0], Cy1 = Cy0 + (Y0[1] - Y1[1]);
-  const int vz12 = (int)rint(vz * R(k2One));
-  const bool mx = sx != 0, my = sy != 0;
+  const Terms2 t = terms2<R>(ox, oy, ox1, oy1, sx, sy, vz);
   const int ny = a.ny;
   const int bxn = min(ix, ix + sx) + 1;  // column index of node base (guard offset 1)
   const int by0 = min(iy, iy + sy);      // base row, -1 .. ny - 1 before wrapping
-  const bool box = bx.use && qw == qw_ref;
-  const long long mul = box ? 1ll : (long long)qw;
-  int rb[3];
+  if (bx.use && qw == qw_ref) {
+    // slot of (comp, row b, column 0) in this lane's copy: row offsets per
+    // lane, component offsets uniform, columns immediate
+    int ro[3];
 #pragma unroll
-  for (int b = 0; b < 3; ++b) {
-    int r = by0 + b - (box ? bx.jbase : 0);
-    r += r < 0 ? ny : 0;
-    r -= r >= ny ? ny : 0;
-    rb[b] = r;
-  }
-  const int c0 = bxn - (box ? bx.xmn : 0);
-  auto add = [&](int comp, int ca, int b, int v) {
-    if (box)
-      atomicAdd(bx.lds + ((size_t)((comp * bx.BY + rb[b]) * bx.BX + c0 + ca) * bx.NC + bx.copy),
-                (unsigned long long)(long long)v);
-    else
-      atomicAdd(a.J[comp] + (size_t)(c0 + ca) * ny + rb[b], (unsigned long long)((long long)v * mul));
-  };
-  const int Sy0 = Y0[0] + Y1[0], Sy1 = Y0[1] + Y1[1], Sy2 = Y0[2] + Y1[2];
-  const int Sx0 = X0[0] + X1[0], Sx1 = X0[1] + X1[1], Sx2 = X0[2] + X1[2];
-  // Jx
-  add(0, 0, 0, __mul24(Cx0, Sy0));
-  add(0, 0, 1, __mul24(Cx0, Sy1));
-  if (my) add(0, 0, 2, __mul24(Cx0, Sy2));
-  if (mx) {
-    add(0, 1, 0, __mul24(Cx1, Sy0));
-    add(0, 1, 1, __mul24(Cx1, Sy1));
-    if (my) add(0, 1, 2, __mul24(Cx1, Sy2));
-  }
-  // Jy
-  add(1, 0, 0, __mul24(Sx0, Cy0));
-  add(1, 1, 0, __mul24(Sx1, Cy0));
-  if (mx) add(1, 2, 0, __mul24(Sx2, Cy0));
-  if (my) {
-    add(1, 0, 1, __mul24(Sx0, Cy1));
-    add(1, 1, 1, __mul24(Sx1, Cy1));
-    if (mx) add(1, 2, 1, __mul24(Sx2, Cy1));
-  }
-  // Jz
-  auto tz = [&](int i, int j) {
-    return __mul24(vz12, (__mul24(X0[i], Y0[j]) + __mul24(X1[i], Y1[j])) >> k2Q);
-  };
-  add(2, 0, 0, tz(0, 0));
-  add(2, 1, 0, tz(1, 0));
-  add(2, 0, 1, tz(0, 1));
-  add(2, 1, 1, tz(1, 1));
-  if (mx) {
-    add(2, 2, 0, tz(2, 0));
-    add(2, 2, 1, tz(2, 1));
-  }
-  if (my) {
-    add(2, 0, 2, tz(0, 2));
-    add(2, 1, 2, tz(1, 2));
-    if (mx) add(2, 2, 2, tz(2, 2));
+    for (int b = 0; b < 3; ++b) {
+      int r = by0 + b - bx.jbase;
+      r += r < 0 ? ny : 0;
+      r -= r >= ny ? ny : 0;
+      ro[b] = r * bx.BX + (bxn - bx.xmn) + bx.copy;
+    }
+    const int P = bx.BY * bx.BX;
+    add_terms2(t, [&](int comp, int ca, int b, int v) {
+      atomicAdd(bx.lds + (ro[b] + comp * P) + ca, (unsigned long long)(long long)v);
+    });
+  } else {
+    int rg[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      int r = by0 + b;
+      r += r < 0 ? ny : 0;
+      r -= r >= ny ? ny : 0;
+      rg[b] = r;
+    }
+    const long long q = qw;
+    add_terms2(t, [&](int comp, int ca, int b, int v) {
+      atomicAdd(a.J[comp] + (size_t)(bxn + ca) * ny + rg[b], (unsigned long long)(q * v));
+    });
   }
 }
 
@@ -413,7 +441,6 @@ __device__ __forceinline__ void push2_tile(const Push2Args<R>& a, int s, int til
   // box: columns xmn - 1 .. xmx + 2, rows of the arc plus one below and two
   // above (or every row, the stencils wrapping onto it)
   Box2 bx;
-  bx.lds = lds;
   bx.xmn = xmn;
   bx.BX = xmx - xmn + 4;
   const int span = dmx - dmn + 4;
@@ -428,13 +455,15 @@ __device__ __forceinline__ void push2_tile(const Push2Args<R>& a, int s, int til
     bx.jbase = 0;
   }
   const int slots = 3 * bx.BX * bx.BY;
+  bx.CS = slots | 1;
   int nc = k2MaxCopies;
-  while (nc > 1 && slots * nc > k2Slots) nc >>= 1;
+  while (nc > 1 && bx.CS * nc > k2Slots) nc >>= 1;
   bx.NC = nc;
-  bx.copy = lane & (nc - 1);
-  bx.use = slots * nc <= k2Slots;
+  bx.use = bx.CS * nc <= k2Slots;
+  bx.lds = lds;
+  bx.copy = (lane & (nc - 1)) * bx.CS;
   if (bx.use)
-    for (int e = tid; e < slots * nc; e += kThreads) lds[e] = 0ull;
+    for (int e = tid; e < bx.CS * nc; e += kThreads) lds[e] = 0ull;
   __syncthreads();
 
   Acc2 acc{0.f, 0.f, 0.f};
@@ -461,7 +490,7 @@ __device__ __forceinline__ void push2_tile(const Push2Args<R>& a, int s, int til
     const long long qw_ref = a.qw_ref[s];
     for (int e = tid; e < slots; e += kThreads) {
       long long v = 0;
-      for (int k = 0; k < bx.NC; ++k) v += (long long)lds[e * bx.NC + k];
+      for (int k = 0; k < bx.NC; ++k) v += (long long)lds[k * bx.CS + e];
       if (v) {
         const int comp = e >= 2 * P ? 2 : (e >= P ? 1 : 0);
         const int rem = e - comp * P;
