@@ -28,14 +28,32 @@ PEAK_HBM_GBS = 8000.0
 TIMING_PERIOD = 8
 
 
-def kernel_hash() -> str:
-    """SHA-256 of the device source the push kernel is built from."""
+KERNEL_SOURCES = {"k_push": ("kernels.hpp", "pic_lib.hip"),
+                  "k_push2": ("kernels.hpp", "kernels2d.hpp", "pic2d_host.inc")}
+
+
+def kernel_hash(kernel: str = "k_push") -> str:
+    """SHA-256 of the device source a push kernel is built from."""
     import hashlib
 
     h = hashlib.sha256()
-    for f in ("kernels.hpp", "pic_lib.hip"):
+    for f in KERNEL_SOURCES[kernel]:
         h.update(open(os.path.join(ROOT, "paper_1008_1685_amd", "csrc", f), "rb").read())
     return h.hexdigest()
+
+
+def stored_traffic(path: str, workload: str, kernel: str):
+    """HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (calibrated
+    on a plain copy), only for the kernel source the counters were taken on."""
+    if not os.path.exists(path):
+        return None
+    try:
+        tj = json.load(open(path))
+        if tj.get("workload") == workload and tj.get("kernel_sha256") == kernel_hash(kernel):
+            return tj.get("bytes_per_launch")
+    except Exception:
+        pass
+    return None
 
 
 def alg_bytes_per_push(precision: str, compensated: bool, rr: bool):
@@ -117,7 +135,7 @@ def time_run_2d(cfg, steps, warmup, timing=TIMING_PERIOD):
     return out
 
 
-def bench_2d(warmup=1280, steps=400):
+def bench_2d(warmup=1280, steps=400, side_runs=True, traffic_json=None):
     """The 2D3V form (2,560 x 1,024 cells, 8.4e6 particles, LP a0 = 500 with
     a 4-wavelength waist), timed from the pulse's arrival at the foil: one
     step = push-deposit, the three field launches, the cell sort every 16
@@ -138,11 +156,15 @@ def bench_2d(warmup=1280, steps=400):
                warmup=warmup,
                roofline=dict(bound="hbm", achieved=nbytes / avg / 1e9, peak=PEAK_HBM_GBS, unit="GB/s",
                              frac=nbytes / avg / 1e9 / PEAK_HBM_GBS, kernel="k_push2",
+                             traffic=stored_traffic(traffic_json or os.path.join(
+                                 ROOT, "profiles", "traffic_d2.json"), "d2", "k_push2"),
                              bytes_per_launch=nbytes, avg_launch_us=avg * 1e6,
                              alg_bytes_per_push=dict(electron=be, ion=bi)),
                kernel_us_per_launch={k: v[0] * 1e3 / max(v[1], 1) for k, v in r["kernels"].items()},
                gauss_int=r["diag1"]["gauss_int"], gauss=r["diag1"]["gauss"],
                energy_balance=r["diag1"]["balance"] / max(r["diag1"]["E_in"], 1e-300))
+    if not side_runs:
+        return out
     side = max(steps // 2, 100)
     r_off = time_run_2d(dict(cfg, rr=False), side, warmup, timing=0)
     r_64 = time_run_2d(dict(cfg, precision="fp64"), side, warmup, timing=0)
@@ -272,11 +294,14 @@ def stress_bench(serve_kwargs, warm=400, window=200, chunk=8, share=0.2):
                 serving_under_load=serving)
 
 
-def write_traffic(fetch, write, cfetch, cwrite, out_path):
-    """profiles/traffic.json from rocprofv3 counter_collection.csv files:
-    FETCH_SIZE and WRITE_SIZE of this benchmark (--steps 50 --warmup 3950
-    --no-side-runs --no-serve) and of a plain 1 GiB device copy
-    (torch b.copy_(a), the calibration of bytes reported per byte moved)."""
+def write_traffic(fetch, write, cfetch, cwrite, out_path, kernel="k_push", workload="c3",
+                  match="k_push"):
+    """A traffic record (profiles/traffic.json, profiles/traffic_d2.json) from
+    rocprofv3 counter_collection.csv files: FETCH_SIZE and WRITE_SIZE of the
+    last 50 launches whose name contains `match` (c3: --steps 50 --warmup 3950
+    --no-side-runs --no-serve; d2: --only-2d --no-side-runs) and of a plain
+    1 GiB device copy (torch b.copy_(a), the calibration of bytes reported
+    per byte moved)."""
     import csv
 
     import numpy as np
@@ -288,9 +313,9 @@ def write_traffic(fetch, write, cfetch, cwrite, out_path):
     f_copy, _ = kib(cfetch, "copyBuffer")
     w_copy, _ = kib(cwrite, "copyBuffer")
     f_factor, w_factor = 2 ** 30 / (f_copy * 1024), 2 ** 30 / (w_copy * 1024)
-    f_push, nf = kib(fetch, "k_push")
-    w_push, nw = kib(write, "k_push")
-    out = dict(workload="c3", kernel="k_push", kernel_sha256=kernel_hash(),
+    f_push, nf = kib(fetch, match)
+    w_push, nw = kib(write, match)
+    out = dict(workload=workload, kernel=kernel, kernel_sha256=kernel_hash(kernel),
                fetch_kib=f_push, write_kib=w_push, fetch_factor=f_factor, write_factor=w_factor,
                read_bytes=f_push * 1024 * f_factor, write_bytes=w_push * 1024 * w_factor,
                bytes_per_launch=f_push * 1024 * f_factor + w_push * 1024 * w_factor,
@@ -315,7 +340,11 @@ def main():
                     help="only run the stress run with the first N serving requests beside it")
     ap.add_argument("--stress-share", type=float, default=0.2,
                     help="duty cycle of the stress run while requests are served (1: unthrottled)")
-    ap.add_argument("--only-2d", action="store_true", help="only run the 2D3V measurement")
+    ap.add_argument("--only-2d", action="store_true",
+                    help="only run the 2D3V measurement (with --no-side-runs: without its RR-off "
+                         "and FP64 runs)")
+    ap.add_argument("--traffic-2d", action="store_true",
+                    help="with --write-traffic: the 2D push kernel on d2 (profiles/traffic_d2.json)")
     ap.add_argument("--serve-only", type=int, default=0, metavar="N",
                     help="only run the serving measurement, on the first N requests")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
@@ -324,7 +353,14 @@ def main():
                     help="write --traffic-json from rocprofv3 counter files and exit")
     args = ap.parse_args()
     if args.write_traffic:
-        write_traffic(*args.write_traffic, args.traffic_json)
+        if args.traffic_2d:
+            path = args.traffic_json
+            if path == os.path.join(ROOT, "profiles", "traffic.json"):
+                path = os.path.join(ROOT, "profiles", "traffic_d2.json")
+            write_traffic(*args.write_traffic, path, kernel="k_push2", workload="d2",
+                          match="k_push2<float>")
+        else:
+            write_traffic(*args.write_traffic, args.traffic_json)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -340,7 +376,7 @@ def main():
         print(json.dumps(dict(serving=serve_bench(n_runs=args.serve_only))), flush=True)
         return
     if args.only_2d:
-        print(json.dumps(dict(pic2d=bench_2d())), flush=True)
+        print(json.dumps(dict(pic2d=bench_2d(side_runs=not args.no_side_runs))), flush=True)
         return
     if args.stress_only:
         print(json.dumps(dict(stress=stress_bench(dict(n_runs=args.stress_only), share=args.stress_share))),
@@ -357,14 +393,7 @@ def main():
     achieved = bytes_per_launch / avg_push_s / 1e9
     # HBM bytes per push launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (calibrated
     # on a plain copy); only valid for the kernel source the counters were taken on
-    traffic = None
-    if os.path.exists(args.traffic_json):
-        try:
-            tj = json.load(open(args.traffic_json))
-            if tj.get("workload") == args.workload and tj.get("kernel_sha256") == kernel_hash():
-                traffic = tj.get("bytes_per_launch")
-        except Exception:
-            traffic = None
+    traffic = stored_traffic(args.traffic_json, args.workload, "k_push")
 
     line = dict(
         metric="particle-pushes/s incl. RR+gather+deposit (% HBM roofline); p50/p99 run latency",
