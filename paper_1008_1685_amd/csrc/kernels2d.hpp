@@ -33,7 +33,7 @@ namespace pic {
 #define PIC2D_PUSH_PPT 8
 #endif
 #ifndef PIC2D_LDS_SLOTS
-#define PIC2D_LDS_SLOTS 4096
+#define PIC2D_LDS_SLOTS 3072
 #endif
 
 constexpr int k2Q = 12;                   // fixed-point bits of a shape weight
@@ -322,6 +322,55 @@ __device__ __forceinline__ void deposit2(const Push2Args<R>& a, const Box2& bx, 
   }
 }
 
+// Fields of one tile staged in LDS: columns x0 .. x0 + SX - 1 (node and
+// half-node columns alike), rows of the tile's arc from one below to one
+// above, SY of them, row fastest per class array.  A particle in cell
+// (ix, iy) reads columns ix - x0 .. + 2 and rows iy - 1 .. iy + 1, which are
+// local rows r0 .. r0 + 2 with r0 = (iy - 1 - row0) mod ny.
+#ifndef PIC2D_FIELD_STAGE
+#define PIC2D_FIELD_STAGE 384
+#endif
+constexpr int k2Stage = PIC2D_FIELD_STAGE;  // staged (column, row) cells per tile, at most
+
+template <typename R>
+struct Stage2 {
+  const R* ez;
+  const NH<R>* nh;
+  const HN<R>* hn;
+  const R* bz;
+  int x0, row0, SY;
+  bool use;
+};
+
+template <typename R>
+__device__ __forceinline__ void gather2_lds(const Stage2<R>& g, int ny, int ix, int iy, R ox, R oy,
+                                            R& ex, R& ey, R& ez, R& bx, R& by, R& bz) {
+  int r0 = iy - 1 - g.row0;
+  r0 += r0 < 0 ? ny : 0;
+  r0 -= r0 >= ny ? ny : 0;
+  const int gb = oy >= R(0.5), hb = ox >= R(0.5);
+  const R fy = gb ? oy - R(0.5) : oy + R(0.5);
+  const R fx = hb ? ox - R(0.5) : ox + R(0.5);
+  const int n0 = (ix - g.x0) * g.SY, n1 = n0 + g.SY;
+  const int q0 = n0 + (hb ? g.SY : 0), q1 = q0 + g.SY;
+  const int rj = r0 + 1, rg = r0 + gb;  // first row, first half-row
+  const R wx0 = R(1) - ox, wy0 = R(1) - oy, vx0 = R(1) - fx, vy0 = R(1) - fy;
+  ez = wx0 * (wy0 * g.ez[n0 + rj] + oy * g.ez[n0 + rj + 1]) +
+       ox * (wy0 * g.ez[n1 + rj] + oy * g.ez[n1 + rj + 1]);
+  {
+    const NH<R> a = g.nh[n0 + rg], b = g.nh[n0 + rg + 1], c = g.nh[n1 + rg], d = g.nh[n1 + rg + 1];
+    ey = wx0 * (vy0 * a.ey + fy * b.ey) + ox * (vy0 * c.ey + fy * d.ey);
+    bx = wx0 * (vy0 * a.bx + fy * b.bx) + ox * (vy0 * c.bx + fy * d.bx);
+  }
+  {
+    const HN<R> a = g.hn[q0 + rj], b = g.hn[q0 + rj + 1], c = g.hn[q1 + rj], d = g.hn[q1 + rj + 1];
+    ex = vx0 * (wy0 * a.ex + oy * b.ex) + fx * (wy0 * c.ex + oy * d.ex);
+    by = vx0 * (wy0 * a.by + oy * b.by) + fx * (wy0 * c.by + oy * d.by);
+  }
+  bz = vx0 * (vy0 * g.bz[q0 + rg] + fy * g.bz[q0 + rg + 1]) +
+       fx * (vy0 * g.bz[q1 + rg] + fy * g.bz[q1 + rg + 1]);
+}
+
 struct Acc2 {
   float rad, esc, stiff;
 };
@@ -331,12 +380,15 @@ struct Acc2 {
 template <typename R, bool RR, bool COMP>
 __device__ __forceinline__ void push2_particle(const Push2Args<R>& a, const SpeciesDev<R>& sp, int s,
                                                unsigned ui, const P2<R>& pd, const Box2& box,
-                                               Acc2& acc) {
+                                               const Stage2<R>& stg, Acc2& acc) {
   if (pd.c == kDead) return;
   const int ymask = (1 << a.ysh) - 1;
   const int ix = pd.c >> a.ysh, iy = pd.c & ymask;
   R ex, ey, ez, bx, by, bz;
-  gather2<R>(a.f, a.ny, ix, iy, pd.ox, pd.oy, ex, ey, ez, bx, by, bz);
+  if (stg.use)
+    gather2_lds<R>(stg, a.ny, ix, iy, pd.ox, pd.oy, ex, ey, ez, bx, by, bz);
+  else
+    gather2<R>(a.f, a.ny, ix, iy, pd.ox, pd.oy, ex, ey, ez, bx, by, bz);
   float rx = pd.rx, ry = pd.ry, rz = pd.rz;
   MomentumOut<R> mo;
   momentum_step<R, RR, COMP, false, true>(pd.ux, pd.uy, pd.uz, ex, ey, ez, by, bz, a.qh[s],
@@ -381,7 +433,7 @@ __device__ __forceinline__ void push2_particle(const Push2Args<R>& a, const Spec
 
 template <typename R, bool RR, bool COMP>
 __device__ __forceinline__ void push2_tile(const Push2Args<R>& a, int s, int tile, int n, int base,
-                                           unsigned long long* lds) {
+                                           unsigned long long* lds, R* fst) {
   __shared__ int s_red[4][kThreads / kLanes];
   __shared__ int s_jref;
   __shared__ double s_acc[3][kThreads / kLanes];
@@ -464,6 +516,44 @@ __device__ __forceinline__ void push2_tile(const Push2Args<R>& a, int s, int til
   bx.copy = (lane & (nc - 1)) * bx.CS;
   if (bx.use)
     for (int e = tid; e < bx.CS * nc; e += kThreads) lds[e] = 0ull;
+
+  // fields of the tile's cells: columns xmn .. xmx + 2, rows of the arc from
+  // one below to one above (every row plus the two wrapped ones when the arc
+  // covers the whole period)
+  R* s_ez = reinterpret_cast<R*>(fst);
+  R* s_bz = s_ez + k2Stage;
+  NH<R>* s_nh = reinterpret_cast<NH<R>*>(s_bz + k2Stage);
+  HN<R>* s_hn = reinterpret_cast<HN<R>*>(s_nh + k2Stage);
+  Stage2<R> stg;
+  stg.ez = s_ez;
+  stg.nh = s_nh;
+  stg.hn = s_hn;
+  stg.bz = s_bz;
+  stg.x0 = xmn;
+  if (span < ny) {
+    stg.SY = span - 1;
+    stg.row0 = bx.jbase;
+  } else {
+    stg.SY = ny + 2;
+    stg.row0 = ny - 1;
+  }
+  const int SX = xmx - xmn + 3;
+  stg.use = SX * stg.SY <= k2Stage;
+  if (stg.use) {
+    for (int e = tid; e < SX * stg.SY; e += kThreads) {
+      const int c = e / stg.SY, r = e - c * stg.SY;
+      const int gx = xmn + c;
+      int gy = stg.row0 + r;
+      gy -= gy >= ny ? ny : 0;
+      gy -= gy >= ny ? ny : 0;
+      const size_t gi = (size_t)gx * ny + gy;
+      const bool node = gx <= a.nx;  // node arrays end at column nx, half-node arrays at nx + 1
+      s_ez[e] = node ? a.f.ez[gi] : R(0);
+      s_nh[e] = node ? a.f.nh[gi] : NH<R>{R(0), R(0)};
+      s_hn[e] = a.f.hn[gi];
+      s_bz[e] = a.f.bz[gi];
+    }
+  }
   __syncthreads();
 
   Acc2 acc{0.f, 0.f, 0.f};
@@ -473,7 +563,7 @@ __device__ __forceinline__ void push2_tile(const Push2Args<R>& a, int s, int til
     const int i = base + k * kThreads + tid;
     P2<R> nxt;
     if (k + 1 < k2PPT) nxt = load2<R, COMP>(sp, i + kThreads, n, cl[k + 1]);
-    push2_particle<R, RR, COMP>(a, sp, s, (unsigned)i, cur, bx, acc);
+    push2_particle<R, RR, COMP>(a, sp, s, (unsigned)i, cur, bx, stg, acc);
     if (k + 1 < k2PPT) cur = nxt;
   }
 
@@ -519,6 +609,7 @@ __device__ __forceinline__ void push2_tile(const Push2Args<R>& a, int s, int til
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_push2(Push2Args<R> a) {
   __shared__ unsigned long long lds[k2Slots];
+  __shared__ R fst[6 * k2Stage];  // staged fields: E_z, B_z, (E_y, B_x), (E_x, B_y)
   const int tile = (int)blockIdx.x;
   const int s = tile < a.tiles0 ? 0 : 1;
   const int tl = s ? tile - a.tiles0 : tile;
@@ -527,11 +618,11 @@ __global__ __launch_bounds__(kThreads) void k_push2(Push2Args<R> a) {
   if (base >= n) return;
   if (s == 0 && a.rr0) {
     if (a.comp)
-      push2_tile<R, true, true>(a, s, tile, n, base, lds);
+      push2_tile<R, true, true>(a, s, tile, n, base, lds, fst);
     else
-      push2_tile<R, true, false>(a, s, tile, n, base, lds);
+      push2_tile<R, true, false>(a, s, tile, n, base, lds, fst);
   } else {
-    push2_tile<R, false, false>(a, s, tile, n, base, lds);
+    push2_tile<R, false, false>(a, s, tile, n, base, lds, fst);
   }
 }
 
