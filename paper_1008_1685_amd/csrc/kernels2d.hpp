@@ -11,10 +11,10 @@
 //               3 x 3 stencil to one of several private copies of an LDS box
 //               covering the tile's cells; the box goes to HBM with one
 //               64-bit atomic per node at the end.
-//   k_field2_b  half step of B (run before and after the E step).
-//   k_field2_e  E step, boundary guards, Poynting bookkeeping, the running
-//               integer charge implied by the current, and the clearing of
-//               the next step's current.
+//   k_field2    one Yee step (B half step, E step, B half step) per tile
+//               with halos recomputed in LDS, boundary guards, Poynting
+//               bookkeeping, the running integer charge implied by the
+//               current, and the clearing of the next step's current.
 //   k_init2, k_diag2_*: quiet start and FP64 diagnostics.
 // The cell sort reuses the 1D kernels (the y offset moves with the particle).
 //
@@ -670,12 +670,13 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter2(SortArgs<R> p) {
 // ---------------------------------------------------------------- fields
 template <typename R>
 struct Field2Args {
-  Fields2Dev<R> f;
+  Fields2Dev<R> in, out;          // E^n, B^n -> E^{n+1}, B^{n+1}
   const long long* J[3];          // current of this step
-  unsigned long long* Jnext[3];   // current of the next step, zeroed by k_field2_e
+  unsigned long long* Jnext[3];   // current of the next step, zeroed here
   long long* cont;                // [(nx + 1) ny] integer charge carried by the current
   double* flux;                   // [3][ny] per row: E_in, E_out_left, E_out_right
-  long long* step;                // device step counter
+  long long* step_dev;            // device step counter, set to step + 1
+  long long step;                 // this step (the laser clock)
   int nx, ny;
   R a, ha, dt;                    // dt/dx, dt/(2 dx), dt
   double dtd, dy;
@@ -685,108 +686,166 @@ struct Field2Args {
   double waist, yc;               // transverse profile exp(-((y - yc) / waist)^2); waist 0: flat
 };
 
-// B^n -> B^{n+1/2} (or B^{n+1/2} -> B^{n+1}) at every interior position; one
-// thread per (column X = 0..nx+1, row j); the last call of a step advances
-// the step counter
-template <typename R>
-__global__ __launch_bounds__(256) void k_field2_b(Field2Args<R> p, int tick) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int ny = p.ny, n = p.nx;
-  if (t >= (long long)(n + 2) * ny) return;
-  const int X = (int)(t / ny), j = (int)(t - (long long)X * ny);
-  const int jp = j + 1 == ny ? 0 : j + 1;
-  const R ha = p.ha;
-  const size_t c = (size_t)X * ny;
-  if (X >= 1 && X <= n) {  // half-node h = X: B_z (half-row j), B_y (row j)
-    const R ey1 = p.f.nh[c + j].ey, ey0 = p.f.nh[c - ny + j].ey;
-    const R ex0 = p.f.hn[c + j].ex, ex1 = p.f.hn[c + jp].ex;
-    p.f.bz[c + j] -= ha * ((ey1 - ey0) - (ex1 - ex0));
-    const R ez1 = p.f.ez[c + j], ez0 = p.f.ez[c - ny + j];
-    st_member<R>(p.f.hn, c + j, 1, p.f.hn[c + j].by + ha * (ez1 - ez0));
-  }
-  if (X <= n) {  // node i = X: B_x (half-row j)
-    const R ez0 = p.f.ez[c + j], ez1 = p.f.ez[c + jp];
-    st_member<R>(p.f.nh, c + j, 1, p.f.nh[c + j].bx - ha * (ez1 - ez0));
-  }
-  if (tick && t == 0) *p.step += 1;
-}
-
 __device__ __forceinline__ double profile2(double y, double yc, double waist) {
   if (waist <= 0.0) return 1.0;
   const double u = (y - yc) / waist;
   return exp(-u * u);
 }
 
-// E^n -> E^{n+1} with J^{n+1/2}, the boundary guards at t_{n+1/2}, per-row
-// boundary fluxes, the running integer charge, and the next current cleared
+// One Yee step on a tile of kFTX columns (X = node i and half-node h = X)
+// by kFTY rows, with halos recomputed: the tile's E^n, B^n (two columns to
+// the left and one to the right, one row below and two above) and J pass
+// through LDS, then B^{n+1/2} (one column and row around the tile), E^{n+1}
+// (one column to the left, one row above) and B^{n+1} at the tile.  Rows are
+// periodic; every local row maps to global row (j0 - 1 + local) mod ny, so
+// a period shorter than the tile just repeats.  The x-end positions apply the
+// boundary guards at t_{n+1/2} and book the Poynting fluxes; each output
+// cell updates its running charge and clears the next step's current.
+constexpr int kFTX = 8, kFTY = 32;
+constexpr int kFAW = kFTX + 3, kFAH = kFTY + 3;  // E^n, B^n region
+constexpr int kFW = kFTX + 2, kFH = kFTY + 2;    // J, B^{n+1/2}, E^{n+1} regions
+static_assert(kFTX * kFTY == 256, "one thread per output cell");
+
 template <typename R>
-__global__ __launch_bounds__(256) void k_field2_e(Field2Args<R> p) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int ny = p.ny, n = p.nx;
-  if (t >= (long long)(n + 2) * ny) return;
-  const int X = (int)(t / ny), j = (int)(t - (long long)X * ny);
-  const int jm = j == 0 ? ny - 1 : j - 1;
-  const R a = p.a, dt = p.dt;
-  const size_t c = (size_t)X * ny;
-  p.Jnext[0][c + j] = 0ull;
-  p.Jnext[1][c + j] = 0ull;
-  p.Jnext[2][c + j] = 0ull;
+__global__ __launch_bounds__(256) void k_field2(Field2Args<R> p) {
+  __shared__ R aEz[kFAW * kFAH], aEy[kFAW * kFAH], aBx[kFAW * kFAH];
+  __shared__ R aEx[kFAW * kFAH], aBy[kFAW * kFAH], aBz[kFAW * kFAH];
+  __shared__ long long sJ[3][kFW * kFH];
+  __shared__ R hBz[kFW * kFH], hBy[kFW * kFH], hBx[kFW * kFH];
+  __shared__ R nEx[kFW * kFH], nEy[kFW * kFH], nEz[kFW * kFH];
+  __shared__ R gL[2][kFH], gR[2][kFH];          // guards (B_z, B_y) at h = 0 and h = nx + 1
+  __shared__ double sIn[2][kFH];                // incident (E_y, E_z) per row
+  const int t = threadIdx.x, n = p.nx, ny = p.ny;
+  const int X0 = blockIdx.x * kFTX, j0 = blockIdx.y * kFTY;
+  const R a = p.a, ha = p.ha, dt = p.dt;
+  auto wrap = [&](int j) {
+    j %= ny;
+    return j < 0 ? j + ny : j;
+  };
+  // ---- load: E^n, B^n on columns X0-2 .. X0+kFTX, rows j0-1 .. j0+kFTY+1
+  for (int e = t; e < kFAW * kFAH; e += 256) {
+    const int lc = e / kFAH, lr = e - lc * kFAH;
+    const int X = X0 - 2 + lc, gj = wrap(j0 - 1 + lr);
+    const size_t gi = (size_t)X * ny + gj;
+    const bool node = X >= 0 && X <= n, half = X >= 0 && X <= n + 1;
+    const NH<R> v = node ? p.in.nh[gi] : NH<R>{R(0), R(0)};
+    const HN<R> w = half ? p.in.hn[gi] : HN<R>{R(0), R(0)};
+    aEz[e] = node ? p.in.ez[gi] : R(0);
+    aEy[e] = v.ey;
+    aBx[e] = v.bx;
+    aEx[e] = w.ex;
+    aBy[e] = w.by;
+    aBz[e] = half ? p.in.bz[gi] : R(0);
+  }
+  // ---- J on columns X0-1 .. X0+kFTX, rows j0-1 .. j0+kFTY
+  for (int e = t; e < kFW * kFH; e += 256) {
+    const int lc = e / kFH, lr = e - lc * kFH;
+    const int X = X0 - 1 + lc, gj = wrap(j0 - 1 + lr);
+    const bool half = X >= 0 && X <= n + 1;
+    sJ[0][e] = half ? p.J[0][(size_t)X * ny + gj] : 0;
+    sJ[1][e] = X <= n + 1 ? p.J[1][(size_t)(X + 1) * ny + gj] : 0;
+    sJ[2][e] = X <= n + 1 ? p.J[2][(size_t)(X + 1) * ny + gj] : 0;
+  }
+  __syncthreads();
+  // ---- B^{n+1/2} on columns X0-1 .. X0+kFTX, rows j0-1 .. j0+kFTY
+  for (int e = t; e < kFW * kFH; e += 256) {
+    const int lc = e / kFH, lr = e - lc * kFH;
+    const int X = X0 - 1 + lc;
+    const int A = (lc + 1) * kFAH + lr, Am = A - kFAH;  // (X, row) and (X - 1, row) in the E^n region
+    R bz = aBz[A], by = aBy[A], bx = aBx[A];
+    if (X >= 1 && X <= n) {
+      bz -= ha * ((aEy[A] - aEy[Am]) - (aEx[A + 1] - aEx[A]));
+      by += ha * (aEz[A] - aEz[Am]);
+    }
+    if (X >= 0 && X <= n) bx -= ha * (aEz[A + 1] - aEz[A]);
+    hBz[e] = bz;
+    hBy[e] = by;
+    hBx[e] = bx;
+  }
+  __syncthreads();
+  // ---- E^{n+1} on columns X0-1 .. X0+kFTX-1, rows j0 .. j0+kFTY (with the guards)
+  const double th = ((double)p.step + 0.5) * p.dtd;
+  const double env = envelope(th, p.tr, p.tf, p.tl);
+  for (int e = t; e < (kFTX + 1) * (kFTY + 1); e += 256) {
+    const int lcx = e / (kFTY + 1), lrx = e - lcx * (kFTY + 1);
+    const int lc = lcx, lr = lrx + 1;  // in the (kFW, kFH) regions
+    const int X = X0 - 1 + lc;
+    const int H = lc * kFH + lr;       // (X, row) in the B, J and E^{n+1} regions
+    const int A = (lc + 1) * kFAH + lr;
+    const R jx = (R)((double)sJ[0][H] * p.sJ), jy = (R)((double)sJ[1][H] * p.sJ);
+    const R jz = (R)((double)sJ[2][H] * p.sJz);
+    nEx[H] = (X >= 1 && X <= n) ? aEx[A] + (a * (hBz[H] - hBz[H - 1]) - dt * jx) : aEx[A];
+    if (X < 0 || X > n) continue;
+    R bz0 = hBz[H], bz1 = hBz[H + kFH], by0 = hBy[H], by1 = hBy[H + kFH];
+    const R ey = aEy[A], ez = aEz[A], d = R(1) + a;
+    if (X == 0) {
+      const int gj = wrap(j0 - 1 + lr);
+      const double ey_in = p.ay * env * sin(th) * profile2((gj + 0.5) * p.dy, p.yc, p.waist);
+      const double ez_in = p.az * env * cos(th) * profile2((double)gj * p.dy, p.yc, p.waist);
+      bz0 = (R(4) * (R)ey_in - R(2) * ey - (R(1) - a) * bz1 + dt * jy) / d;
+      by0 = (R(2) * ez - (R(1) - a) * by1 - dt * jz - R(4) * (R)ez_in) / d;
+      gL[0][lr] = bz0;
+      gL[1][lr] = by0;
+      sIn[0][lr] = ey_in;
+      sIn[1][lr] = ez_in;
+    }
+    if (X == n) {
+      bz1 = (R(2) * ey - (R(1) - a) * bz0 - dt * jy) / d;
+      by1 = (R(-2) * ez - (R(1) - a) * by0 + dt * jz) / d;
+      gR[0][lr] = bz1;
+      gR[1][lr] = by1;
+    }
+    nEy[H] = ey - (a * (bz1 - bz0) + dt * jy);
+    nEz[H] = ez + (a * ((by1 - by0) - (hBx[H] - hBx[H - 1])) - dt * jz);
+  }
+  __syncthreads();
+  // ---- B^{n+1}, outputs, bookkeeping: one thread per cell of the tile
+  const int X = X0 + t / kFTY, j = j0 + (t % kFTY);
+  if (blockIdx.x == 0 && blockIdx.y == 0 && t == 0) *p.step_dev = p.step + 1;
+  if (X > n + 1 || j >= ny) return;
+  const int lc = X - X0 + 1, lr = j - j0 + 1;
+  const int H = lc * kFH + lr, A = (lc + 1) * kFAH + lr;
+  const size_t gi = (size_t)X * ny + j;
+  R bz, by;
+  if (X >= 1 && X <= n) {
+    bz = hBz[H] - ha * ((nEy[H] - nEy[H - kFH]) - (nEx[H + 1] - nEx[H]));
+    by = hBy[H] + ha * (nEz[H] - nEz[H - kFH]);
+  } else {  // guards keep their t_{n+1/2} value
+    bz = X == 0 ? gL[0][lr] : gR[0][lr];
+    by = X == 0 ? gL[1][lr] : gR[1][lr];
+  }
+  p.out.bz[gi] = bz;
+  p.out.hn[gi] = HN<R>{nEx[H], by};
+  p.Jnext[0][gi] = 0ull;
+  p.Jnext[1][gi] = 0ull;
+  p.Jnext[2][gi] = 0ull;
   if (X == n + 1) {
-    p.Jnext[1][c + ny + j] = 0ull;
-    p.Jnext[2][c + ny + j] = 0ull;
+    p.Jnext[1][gi + ny] = 0ull;
+    p.Jnext[2][gi + ny] = 0ull;
+    return;
   }
-  if (X >= 1 && X <= n) {  // E_x at half-node h = X, row j
-    const R jx = (R)((double)p.J[0][c + j] * p.sJ);
-    const R ex = p.f.hn[c + j].ex + (a * (p.f.bz[c + j] - p.f.bz[c + jm]) - dt * jx);
-    st_member<R>(p.f.hn, c + j, 0, ex);
-  }
-  if (X > n) return;
-  // node i = X: E_y (half-row j), E_z (row j)
-  const R jy = (R)((double)p.J[1][c + ny + j] * p.sJ);
-  const R jz = (R)((double)p.J[2][c + ny + j] * p.sJz);
-  const NH<R> e = p.f.nh[c + j];
-  const R ez = p.f.ez[c + j];
-  R bz0 = p.f.bz[c + j], bz1 = p.f.bz[c + ny + j];
-  R by0 = p.f.hn[c + j].by, by1 = p.f.hn[c + ny + j].by;
-  const R bxm = p.f.nh[c + jm].bx;
-  const R d = R(1) + a;
-  double ey_in = 0.0, ez_in = 0.0;
-  if (X == 0) {  // left guards (h = 0) with the incident wave
-    const double th = ((double)*p.step + 0.5) * p.dtd;
-    const double f = envelope(th, p.tr, p.tf, p.tl);
-    ey_in = p.ay * f * sin(th) * profile2((j + 0.5) * p.dy, p.yc, p.waist);
-    ez_in = p.az * f * cos(th) * profile2((double)j * p.dy, p.yc, p.waist);
-    bz0 = (R(4) * (R)ey_in - R(2) * e.ey - (R(1) - a) * bz1 + dt * jy) / d;
-    by0 = (R(2) * ez - (R(1) - a) * by1 - dt * jz - R(4) * (R)ez_in) / d;
-    p.f.bz[c + j] = bz0;
-    st_member<R>(p.f.hn, c + j, 1, by0);
-  }
-  if (X == n) {  // right guards (h = n + 1)
-    bz1 = (R(2) * e.ey - (R(1) - a) * bz0 - dt * jy) / d;
-    by1 = (R(-2) * ez - (R(1) - a) * by0 + dt * jz) / d;
-    p.f.bz[c + ny + j] = bz1;
-    st_member<R>(p.f.hn, c + ny + j, 1, by1);
-  }
-  const R ey_new = e.ey - (a * (bz1 - bz0) + dt * jy);
-  const R ez_new = ez + (a * ((by1 - by0) - (e.bx - bxm)) - dt * jz);
-  st_member<R>(p.f.nh, c + j, 0, ey_new);
-  p.f.ez[c + j] = ez_new;
+  // node i = X
+  const R bx = hBx[H] - ha * (nEz[H + 1] - nEz[H]);
+  p.out.ez[gi] = nEz[H];
+  p.out.nh[gi] = NH<R>{nEy[H], bx};
+  const long long div = (sJ[0][H + kFH] - sJ[0][H]) + (sJ[1][H] - sJ[1][H - 1]);
+  p.cont[gi] -= div;
   if (X == 0) {
-    const double eyl = 0.5 * ((double)e.ey + (double)ey_new), ezl = 0.5 * ((double)ez + (double)ez_new);
-    const double bzl = 0.5 * ((double)bz0 + (double)bz1), byl = 0.5 * ((double)by0 + (double)by1);
+    const double ey_in = sIn[0][lr], ez_in = sIn[1][lr];
+    const double eyl = 0.5 * ((double)aEy[A] + (double)nEy[H]), ezl = 0.5 * ((double)aEz[A] + (double)nEz[H]);
+    const double bzl = 0.5 * ((double)gL[0][lr] + (double)hBz[H + kFH]);
+    const double byl = 0.5 * ((double)gL[1][lr] + (double)hBy[H + kFH]);
     const double L1 = eyl - bzl, L2 = ezl + byl;
     p.flux[j] += p.dtd * p.dy * (ey_in * ey_in + ez_in * ez_in);
     p.flux[ny + j] += p.dtd * p.dy * 0.25 * (L1 * L1 + L2 * L2);
   }
   if (X == n) {
-    const double eyr = 0.5 * ((double)e.ey + (double)ey_new), ezr = 0.5 * ((double)ez + (double)ez_new);
-    const double bzr = 0.5 * ((double)bz0 + (double)bz1), byr = 0.5 * ((double)by0 + (double)by1);
+    const double eyr = 0.5 * ((double)aEy[A] + (double)nEy[H]), ezr = 0.5 * ((double)aEz[A] + (double)nEz[H]);
+    const double bzr = 0.5 * ((double)hBz[H] + (double)gR[0][lr]);
+    const double byr = 0.5 * ((double)hBy[H] + (double)gR[1][lr]);
     const double R1 = eyr + bzr, R2 = ezr - byr;
     p.flux[2 * ny + j] += p.dtd * p.dy * 0.25 * (R1 * R1 + R2 * R2);
   }
-  // charge moved onto node (X, j) by this step's current
-  const long long div = (p.J[0][c + ny + j] - p.J[0][c + j]) + (p.J[1][c + ny + j] - p.J[1][c + ny + jm]);
-  p.cont[c + j] -= div;
 }
 
 // ---------------------------------------------------------------- init
