@@ -30,7 +30,7 @@
 namespace pic {
 
 #ifndef PIC2D_PUSH_PPT
-#define PIC2D_PUSH_PPT 8
+#define PIC2D_PUSH_PPT 4
 #endif
 #ifndef PIC2D_LDS_SLOTS
 #define PIC2D_LDS_SLOTS 3072
@@ -606,8 +606,17 @@ __device__ __forceinline__ void push2_tile(const Push2Args<R>& a, int s, int til
 }
 
 // one work-group per tile
+#ifndef PIC2D_PUSH_MIN_WAVES
+#define PIC2D_PUSH_MIN_WAVES 0
+#endif
+#if PIC2D_PUSH_MIN_WAVES > 0
+#define PIC2D_PUSH_BOUNDS __launch_bounds__(kThreads, PIC2D_PUSH_MIN_WAVES)
+#else
+#define PIC2D_PUSH_BOUNDS __launch_bounds__(kThreads)
+#endif
+
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_push2(Push2Args<R> a) {
+__global__ PIC2D_PUSH_BOUNDS void k_push2(Push2Args<R> a) {
   __shared__ unsigned long long lds[k2Slots];
   __shared__ R fst[6 * k2Stage];  // staged fields: E_z, B_z, (E_y, B_x), (E_x, B_y)
   const int tile = (int)blockIdx.x;
