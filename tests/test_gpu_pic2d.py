@@ -293,8 +293,9 @@ def test_laser_foil_run_matches_oracle_budget(precision):
 # --------------------------------------------------------------------------- full size
 def test_full_size_push_on_samples():
     # the 2D workload of the benchmark (2,560 x 1,024 cells, 8.4e6 particles)
-    # in the interaction: sampled momenta against the oracle, every cell and
-    # offset against the contract, exact charge continuity over the run
+    # in the interaction: sampled momenta against the oracle, every cell,
+    # offset and current term against the contract, exact charge continuity
+    # over the run
     cfg = preset2d("d2")
     run = _run(cfg)
     run.step(1344)  # 10.5 periods: the pulse is on the foil
@@ -325,5 +326,20 @@ def test_full_size_push_on_samples():
         scale = np.maximum.reduce([nrm(u0), nrm(uL), nrm(un), abs(sim.qm[s]) * sim.dt * nrm(E),
                                    nrm(un - uL), np.full(len(k), 1e-2)])
         assert float((nrm(ug - un) / scale).max()) <= 1e-5
+    # every particle's current, from the contract, against the GPU's arrays
+    nx, ny = sim.nx, sim.ny
+    J = [np.zeros((nx + 2, ny), np.int64), np.zeros((nx + 3, ny), np.int64),
+         np.zeros((nx + 3, ny), np.int64)]
+    for s, Z in ((0, -1), (1, 1)):
+        a, b = before[f"sp{s}"], after[f"sp{s}"]
+        ix, iy = run.decode(a["cell"])
+        m = contract2d.move(ix, iy, a["ox"], a["oy"], b["ux"], b["uy"], b["uz"], cfg["cfl"], ny)
+        qw = contract2d.charge_weight(a["w"], sim.w_ref, Z)
+        for k, arr in enumerate(contract2d.deposit(ix, iy, a["ox"], a["oy"], m[4], m[5], m[2], m[3],
+                                                   m[8], qw, nx, ny)):
+            J[k] += arr
+    assert np.array_equal(after["Jx_int"], J[0])
+    assert np.array_equal(after["Jy_int"], J[1])
+    assert np.array_equal(after["Jz_int"], J[2])
     run.field_advance()
     assert run.diag()["gauss_int"] == 0
