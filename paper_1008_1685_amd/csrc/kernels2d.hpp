@@ -7,10 +7,11 @@
 // Kernels:
 //   k_push2     gather -> Boris -> RR (electrons) -> 2D move -> fixed-point
 //               Esirkepov deposit, one thread per particle over cell-sorted
-//               tiles.  Each lane adds the non-zero terms of its particle's
-//               3 x 3 stencil to one of several private copies of an LDS box
-//               covering the tile's cells; the box goes to HBM with one
-//               64-bit atomic per node at the end.
+//               tiles of 1,024.  A tile first stages the fields of its cells
+//               in LDS and gathers from there; each lane adds the non-zero
+//               terms of its particle's 3 x 3 stencil to one of several
+//               private copies of an LDS box covering the tile's cells; the
+//               box goes to HBM with one 64-bit atomic per node at the end.
 //   k_field2    one Yee step (B half step, E step, B half step) per tile
 //               with halos recomputed in LDS, boundary guards, Poynting
 //               bookkeeping, the running integer charge implied by the
@@ -63,13 +64,6 @@ struct Fields2Dev {
   HN<R>* hn;   // [(nx + 2) ny]  half-node, row
   R* bz;       // [(nx + 2) ny]  half-node, half-row
 };
-
-// write one member of an interleaved pair without touching the other (a
-// neighbouring thread may be reading it)
-template <typename R, typename P>
-__device__ __forceinline__ void st_member(P* base, size_t i, int m, R v) {
-  reinterpret_cast<R*>(base)[2 * i + m] = v;
-}
 
 template <typename R>
 struct Push2Args {
@@ -710,7 +704,10 @@ __device__ __forceinline__ double profile2(double y, double yc, double waist) {
 // a period shorter than the tile just repeats.  The x-end positions apply the
 // boundary guards at t_{n+1/2} and book the Poynting fluxes; each output
 // cell updates its running charge and clears the next step's current.
-constexpr int kFTX = 8, kFTY = 32;
+#ifndef PIC2D_FIELD_TX
+#define PIC2D_FIELD_TX 8
+#endif
+constexpr int kFTX = PIC2D_FIELD_TX, kFTY = 256 / PIC2D_FIELD_TX;
 constexpr int kFAW = kFTX + 3, kFAH = kFTY + 3;  // E^n, B^n region
 constexpr int kFW = kFTX + 2, kFH = kFTY + 2;    // J, B^{n+1/2}, E^{n+1} regions
 static_assert(kFTX * kFTY == 256, "one thread per output cell");
