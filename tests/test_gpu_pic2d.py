@@ -115,6 +115,8 @@ def _shuffle_within(p, block, seed):
     (40000, 9000, 2.0, "tiles", False),      # compact tiles, spread waves: per-lane LDS adds
     (3000, 900, 2.0, "none", False),         # unsorted: tiles span the grid, HBM atomics
     (40000, 9000, 2.0, "sorted", True),      # weights other than the reference weight
+    (5000, 1500, 2 / 32, "sorted", False),   # 2 rows: every stencil wraps the period twice
+    (5000, 1500, 3 / 32, "tiles", False),    # 3 rows: cell keys with unused row codes
 ])
 def test_move_and_deposit_bit_exact_without_fields(n_e, n_i, box_y, order, mixed_w):
     # E = B = 0: the push leaves u unchanged, so cells, offsets and currents
@@ -210,9 +212,10 @@ def test_push_currents_conserve_charge_exactly():
 
 
 # --------------------------------------------------------------------------- fields
-@pytest.mark.parametrize("pol,waist", [("LP", 0.6), ("CP", 0.0)])
-def test_field_advance_matches_oracle(pol, waist):
-    cfg = preset2d("d1", box_x=3.0, box_y=1.0, x_foil=1.0, pol=pol, waist=waist, a0=300.0)
+@pytest.mark.parametrize("pol,waist,box_y", [("LP", 0.6, 1.0), ("CP", 0.0, 1.0),
+                                             ("CP", 0.3, 37 / 32)])  # 37 rows: partial tiles
+def test_field_advance_matches_oracle(pol, waist, box_y):
+    cfg = preset2d("d1", box_x=3.0, box_y=box_y, x_foil=1.0, pol=pol, waist=waist, a0=300.0)
     sim = _oracle(cfg)
     nx, ny = sim.nx, sim.ny
     f = random_fields2d(7, nx, ny, 50.0)
