@@ -141,7 +141,9 @@ pic_status pic2d_sort(struct pic2d_run* run, void* stream);
 /* Diagnostics (FP64), as pic_diag_out; energies per unit length in z.
  * gauss: max |div E - rho| over nodes 1..nx-1 (field units, rho from the
  * particles' fixed-point charge); gauss_int: max |charge_int - charge of the
- * particles| over nodes 0..nx, exact integers (expect 0).  Blocking. */
+ * particles| over nodes 1..nx-1, exact integers (expect 0; the end nodes
+ * keep the share of removed particles' last shapes that lay inside).
+ * Blocking. */
 pic_status pic2d_diag(struct pic2d_run* run, pic_diag_out* out, void* stream);
 
 pic_status pic2d_get_info(const struct pic2d_run* run, pic2d_info* out);

@@ -951,7 +951,7 @@ __global__ __launch_bounds__(256) void k_diag2_particles(Diag2Args<R> p) {
 
 // field energies, Gauss residual from the fields and the particles' charge,
 // and the largest difference between that charge and the one the current
-// carried (exact integers: expect 0)
+// carried, over interior nodes (exact integers: expect 0)
 template <typename R>
 __global__ __launch_bounds__(256) void k_diag2_fields(Diag2Args<R> p) {
   __shared__ double sh[4];
@@ -970,10 +970,12 @@ __global__ __launch_bounds__(256) void k_diag2_fields(Diag2Args<R> p) {
       const double ey = e.ey, ez = p.f.ez[c + j], bxv = e.bx;
       ue += wn * (ey * ey + ez * ez);
       ub += wn * bxv * bxv;
-      long long dc = p.cont[c + j] - p.rho[c + j];
-      dc = dc < 0 ? -dc : dc;
-      cmax = dc > cmax ? dc : cmax;
       if (X >= 1 && X <= n - 1) {
+        // interior nodes: a particle removed at an x end leaves part of its
+        // last shape on the end node, which the current never takes away
+        long long dc = p.cont[c + j] - p.rho[c + j];
+        dc = dc < 0 ? -dc : dc;
+        cmax = dc > cmax ? dc : cmax;
         const int jm = j == 0 ? ny - 1 : j - 1;
         const double divE = ((double)p.f.hn[c + ny + j].ex - (double)p.f.hn[c + j].ex) / p.dx +
                             ((double)e.ey - (double)p.f.nh[c + jm].ey) / p.dx;
