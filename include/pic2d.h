@@ -65,6 +65,14 @@
 extern "C" {
 #endif
 
+/* Field advance kernels.  TILES: work-groups of 8 columns x 32 rows, each
+ * loading its tile with halos into LDS; any period.  STRIPS: a work-group
+ * owns a strip of columns and the whole period (one thread per row, at most
+ * 1024 rows in FP32, 512 in FP64) and marches along x, reading every value
+ * once; automatic where it fits. */
+#define PIC2D_FIELD_TILES 1
+#define PIC2D_FIELD_STRIPS 2
+
 typedef struct pic2d_config {
   uint32_t struct_size;      /* sizeof(pic2d_config) of the caller */
   int32_t precision;         /* PIC_FP32 or PIC_FP64 */
@@ -84,7 +92,8 @@ typedef struct pic2d_config {
   double thickness;          /* foil thickness, wavelengths (the foil fills y) */
   double mass_ratio;         /* ion / electron mass */
   int32_t sort_interval;     /* steps between sorts (>= 1) */
-  int32_t reserved;
+  int32_t field_kernel;      /* field advance: 0 automatic, PIC2D_FIELD_TILES or
+                                PIC2D_FIELD_STRIPS (both compute the same step) */
   uint64_t seed;             /* quiet-start jitter seed */
   double jitter;             /* in [0, 1] */
   int64_t capacity;          /* particles per species to reserve; 0 = foil count */
@@ -100,6 +109,8 @@ typedef struct pic2d_info {
   int64_t step;
   int32_t tile;              /* particles per push work-group */
   int32_t lds_slots;         /* 64-bit LDS current accumulators per push work-group */
+  int32_t field_kernel;      /* the field advance in use: PIC2D_FIELD_TILES or _STRIPS */
+  int32_t field_blocks;      /* its work-groups per launch */
 } pic2d_info;
 
 /* Particle arrays for state I/O: as pic_species_state, with two offsets. */

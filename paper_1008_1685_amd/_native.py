@@ -150,7 +150,7 @@ class Pic2dConfig(C.Structure):
         ("thickness", C.c_double),
         ("mass_ratio", C.c_double),
         ("sort_interval", C.c_int32),
-        ("reserved", C.c_int32),
+        ("field_kernel", C.c_int32),
         ("seed", C.c_uint64),
         ("jitter", C.c_double),
         ("capacity", C.c_int64),
@@ -172,6 +172,8 @@ class Pic2dInfo(C.Structure):
         ("step", C.c_int64),
         ("tile", C.c_int32),
         ("lds_slots", C.c_int32),
+        ("field_kernel", C.c_int32),
+        ("field_blocks", C.c_int32),
     ]
 
 

@@ -16,6 +16,10 @@
 //               with halos recomputed in LDS, boundary guards, Poynting
 //               bookkeeping, the running integer charge implied by the
 //               current, and the clearing of the next step's current.
+//   k_field2m   the same step in column-marching form: a work-group owns a
+//               strip of columns and the whole period (one thread per row)
+//               and streams along x, reading each value once; used where
+//               the period fits one work-group.
 //   k_init2, k_diag2_*: quiet start and FP64 diagnostics.
 // The cell sort reuses the 1D kernels (the y offset moves with the particle).
 //
@@ -851,6 +855,188 @@ __global__ __launch_bounds__(256) void k_field2(Field2Args<R> p) {
     const double byr = 0.5 * ((double)hBy[H] + (double)gR[1][lr]);
     const double R1 = eyr + bzr, R2 = ezr - byr;
     p.flux[2 * ny + j] += p.dtd * p.dy * 0.25 * (R1 * R1 + R2 * R2);
+  }
+}
+
+// One Yee step, column-marching form, for periods of at most kFMRows<R>
+// rows: a work-group owns all ny rows (one thread each) of a strip of
+// columns [Xs, Xe) and walks along x.  At column c it forms B^{n+1/2} at c,
+// E^{n+1} at c - 1 and B^{n+1} at c - 2 (with the outputs, running charge
+// and next current of that column), while the loads of column c + 1 are in
+// flight.  Every value is read once, plus the three columns a strip shares
+// with its neighbours.  The row neighbours j + 1 and j - 1 (periodic) pass
+// through LDS slots indexed by row, double-buffered by column parity, so
+// one barrier per column orders them.  The arithmetic is that of k_field2,
+// term by term.
+template <typename R>
+constexpr int kFMRows = sizeof(R) == 4 ? 1024 : 512;
+
+template <typename R>
+__host__ __device__ constexpr size_t field2m_lds(int ny) {
+  return 2 * (size_t)ny * (6 * sizeof(R) + sizeof(long long));
+}
+
+template <typename R>
+__global__ __launch_bounds__(kFMRows<R>) void k_field2m(Field2Args<R> p) {
+  extern __shared__ __align__(16) unsigned char fsm[];
+  const int n = p.nx, ny = p.ny, j = threadIdx.x;
+  const bool live = j < ny;
+  const int jp = j + 1 >= ny ? 0 : j + 1, jm = !live ? 0 : (j == 0 ? ny - 1 : j - 1);
+  // strip of this block: columns [Xs, Xe), widths differing by at most one
+  const int nb = gridDim.x, s = blockIdx.x, ncol = n + 2;
+  const int Xs = (int)((long long)s * ncol / nb), Xe = (int)((long long)(s + 1) * ncol / nb);
+  if (s == 0 && j == 0) *p.step_dev = p.step + 1;
+  R* xr = (R*)fsm;                                              // [2][6][ny]
+  long long* xj = (long long*)(fsm + 2 * 6 * (size_t)ny * sizeof(R));  // [2][ny]
+  const R a = p.a, ha = p.ha, dt = p.dt, z = R(0);
+  // column state, by age at the top of the iteration for column c:
+  R ex0 = z, ey0 = z, ez0 = z, bx0 = z, by0c = z, bz0c = z;   // E^n, B^n (c)
+  R ex1 = z, ey1 = z, ez1 = z;                                // E^n (c - 1)
+  R ey2 = z, ez2 = z;                                         // E^n (c - 2)
+  R hbz1 = z, hby1 = z, hbx1 = z, hbz2 = z, hby2 = z, hbx2 = z;  // B^{n+1/2} (c - 1), (c - 2)
+  R nex2 = z, ney2 = z, nez2 = z, ney3 = z, nez3 = z;        // E^{n+1} (c - 2), (c - 3)
+  long long jc0 = 0, jc1 = 0, jc2 = 0;                        // J (c)
+  long long jp0 = 0, jp1 = 0, jp2 = 0;                        // J (c - 1)
+  long long jq0 = 0, jq1 = 0;                                 // J_x, J_y (c - 2)
+  long long cn2 = 0;                                          // running charge (c - 2)
+  R gl0 = z, gl1 = z, gr0 = z, gr1 = z;                       // x-end guards at t_{n+1/2}
+  double ey_in = 0.0, ez_in = 0.0;
+  // next column's loads
+  R fez = z, fbz = z;
+  NH<R> fnh{z, z};
+  HN<R> fhn{z, z};
+  long long fj0 = 0, fj1 = 0, fj2 = 0, fcn = 0;
+  auto load_col = [&](int col) {
+    const bool nd = col >= 0 && col <= n, hf = col >= 0 && col <= n + 1;
+    const size_t gi = (size_t)(col < 0 ? 0 : col) * ny + j;
+    fez = live && nd ? p.in.ez[gi] : z;
+    fnh = live && nd ? p.in.nh[gi] : NH<R>{z, z};
+    fhn = live && hf ? p.in.hn[gi] : HN<R>{z, z};
+    fbz = live && hf ? p.in.bz[gi] : z;
+    fj0 = live && hf ? p.J[0][gi] : 0;
+    const bool jy = live && col >= -1 && col <= n + 1;
+    const size_t gk = (size_t)(col + 1 < 0 ? 0 : col + 1) * ny + j;
+    fj1 = jy ? p.J[1][gk] : 0;
+    fj2 = jy ? p.J[2][gk] : 0;
+  };
+  load_col(Xs - 2);
+  ex0 = fhn.ex; ey0 = fnh.ey; ez0 = fez; bx0 = fnh.bx; by0c = fhn.by; bz0c = fbz;
+  jc0 = fj0; jc1 = fj1; jc2 = fj2;
+  const double th = ((double)p.step + 0.5) * p.dtd;
+  for (int c = Xs - 2; c <= Xe + 1; ++c) {
+    // loads for the next iterations: E^n, B^n, J of column c + 1 (needed up
+    // to column Xe), the running charge of column c - 1 (output next)
+    if (c + 1 <= Xe) load_col(c + 1);
+    const int xo = c - 1;  // output column of the next iteration
+    fcn = live && xo >= Xs && xo < Xe && xo <= n ? p.cont[(size_t)xo * ny + j] : 0;
+    // publish the values rows j - 1 and j + 1 take from this row
+    R* X = xr + (size_t)(c & 1) * 6 * ny;
+    long long* XJ = xj + (size_t)(c & 1) * ny;
+    if (live) {
+      X[j] = ex0;
+      X[ny + j] = ez0;
+      X[2 * ny + j] = hbz1;
+      X[3 * ny + j] = hbx1;
+      X[4 * ny + j] = nex2;
+      X[5 * ny + j] = nez2;
+      XJ[j] = jq1;
+    }
+    __syncthreads();
+    const R exn = X[jp], ezn = X[ny + jp];           // E^n (c) at j + 1
+    const R hbzm = X[2 * ny + jm], hbxm = X[3 * ny + jm];  // B^{n+1/2} (c - 1) at j - 1
+    const R nexn = X[4 * ny + jp], nezn = X[5 * ny + jp];  // E^{n+1} (c - 2) at j + 1
+    const long long j1m = XJ[jm];                    // J_y (c - 2) at j - 1
+    // B^{n+1/2} at column c
+    R hbz0 = bz0c, hby0 = by0c, hbx0 = bx0;
+    if (c >= 1 && c <= n) {
+      hbz0 -= ha * ((ey0 - ey1) - (exn - ex0));
+      hby0 += ha * (ez0 - ez1);
+    }
+    if (c >= 0 && c <= n) hbx0 -= ha * (ezn - ez0);
+    // E^{n+1} at column c - 1
+    R nex1 = z, ney1 = z, nez1 = z;
+    const int Xn = c - 1;
+    if (Xn >= Xs - 1 && Xn <= Xe - 1) {
+      const R jx = (R)((double)jp0 * p.sJ), jy = (R)((double)jp1 * p.sJ);
+      const R jz = (R)((double)jp2 * p.sJz);
+      nex1 = (Xn >= 1 && Xn <= n) ? ex1 + (a * (hbz1 - hbzm) - dt * jx) : ex1;
+      if (Xn >= 0 && Xn <= n) {
+        R bz0 = hbz1, bz1 = hbz0, by0 = hby1, by1 = hby0;
+        const R ey = ey1, ez = ez1, d = R(1) + a;
+        if (Xn == 0) {
+          const double env = envelope(th, p.tr, p.tf, p.tl);
+          ey_in = p.ay * env * sin(th) * profile2((j + 0.5) * p.dy, p.yc, p.waist);
+          ez_in = p.az * env * cos(th) * profile2((double)j * p.dy, p.yc, p.waist);
+          bz0 = (R(4) * (R)ey_in - R(2) * ey - (R(1) - a) * bz1 + dt * jy) / d;
+          by0 = (R(2) * ez - (R(1) - a) * by1 - dt * jz - R(4) * (R)ez_in) / d;
+          gl0 = bz0;
+          gl1 = by0;
+        }
+        if (Xn == n) {
+          bz1 = (R(2) * ey - (R(1) - a) * bz0 - dt * jy) / d;
+          by1 = (R(-2) * ez - (R(1) - a) * by0 + dt * jz) / d;
+          gr0 = bz1;
+          gr1 = by1;
+        }
+        ney1 = ey - (a * (bz1 - bz0) + dt * jy);
+        nez1 = ez + (a * ((by1 - by0) - (hbx1 - hbxm)) - dt * jz);
+      }
+    }
+    // B^{n+1} and the outputs at column c - 2
+    const int Xo = c - 2;
+    if (live && Xo >= Xs && Xo < Xe) {
+      const size_t gi = (size_t)Xo * ny + j;
+      R bz, by;
+      if (Xo >= 1 && Xo <= n) {
+        bz = hbz2 - ha * ((ney2 - ney3) - (nexn - nex2));
+        by = hby2 + ha * (nez2 - nez3);
+      } else {  // guards keep their t_{n+1/2} value
+        bz = Xo == 0 ? gl0 : gr0;
+        by = Xo == 0 ? gl1 : gr1;
+      }
+      p.out.bz[gi] = bz;
+      p.out.hn[gi] = HN<R>{nex2, by};
+      p.Jnext[0][gi] = 0ull;
+      p.Jnext[1][gi] = 0ull;
+      p.Jnext[2][gi] = 0ull;
+      if (Xo == n + 1) {
+        p.Jnext[1][gi + ny] = 0ull;
+        p.Jnext[2][gi + ny] = 0ull;
+      } else {
+        const R bx = hbx2 - ha * (nezn - nez2);
+        p.out.ez[gi] = nez2;
+        p.out.nh[gi] = NH<R>{ney2, bx};
+        const long long div = (jp0 - jq0) + (jq1 - j1m);
+        p.cont[gi] = cn2 - div;
+        if (Xo == 0) {
+          const double eyl = 0.5 * ((double)ey2 + (double)ney2), ezl = 0.5 * ((double)ez2 + (double)nez2);
+          const double bzl = 0.5 * ((double)gl0 + (double)hbz1);
+          const double byl = 0.5 * ((double)gl1 + (double)hby1);
+          const double L1 = eyl - bzl, L2 = ezl + byl;
+          p.flux[j] += p.dtd * p.dy * (ey_in * ey_in + ez_in * ez_in);
+          p.flux[ny + j] += p.dtd * p.dy * 0.25 * (L1 * L1 + L2 * L2);
+        }
+        if (Xo == n) {
+          const double eyr = 0.5 * ((double)ey2 + (double)ney2), ezr = 0.5 * ((double)ez2 + (double)nez2);
+          const double bzr = 0.5 * ((double)hbz2 + (double)gr0);
+          const double byr = 0.5 * ((double)hby2 + (double)gr1);
+          const double R1 = eyr + bzr, R2 = ezr - byr;
+          p.flux[2 * ny + j] += p.dtd * p.dy * 0.25 * (R1 * R1 + R2 * R2);
+        }
+      }
+    }
+    // age the column state by one
+    ey2 = ey1; ez2 = ez1;
+    ex1 = ex0; ey1 = ey0; ez1 = ez0;
+    ex0 = fhn.ex; ey0 = fnh.ey; ez0 = fez; bx0 = fnh.bx; by0c = fhn.by; bz0c = fbz;
+    hbz2 = hbz1; hby2 = hby1; hbx2 = hbx1;
+    hbz1 = hbz0; hby1 = hby0; hbx1 = hbx0;
+    ney3 = ney2; nez3 = nez2;
+    nex2 = nex1; ney2 = ney1; nez2 = nez1;
+    jq0 = jp0; jq1 = jp1;
+    jp0 = jc0; jp1 = jc1; jp2 = jc2;
+    jc0 = fj0; jc1 = fj1; jc2 = fj2;
+    cn2 = fcn;
   }
 }
 

@@ -13,6 +13,9 @@ _CFG_KEYS = ("lambda_um", "cells_per_lambda", "ppc_x", "ppc_y", "box_x", "box_y"
              "sort_interval", "seed", "jitter")
 
 
+FIELD_KERNELS = {"auto": 0, "tiles": 1, "strips": 2}
+
+
 def make_config(cfg: dict, capacity: int = 0) -> N.Pic2dConfig:
     c = N.Pic2dConfig()
     c.struct_size = C.sizeof(N.Pic2dConfig)
@@ -23,6 +26,7 @@ def make_config(cfg: dict, capacity: int = 0) -> N.Pic2dConfig:
     c.rr = 1 if cfg["rr"] else 0
     c.rr_compensated = 1 if cfg.get("rr_compensated", True) else 0
     c.capacity = int(capacity)
+    c.field_kernel = FIELD_KERNELS[cfg.get("field_kernel", "auto")]
     return c
 
 
@@ -94,7 +98,9 @@ class Run2D:
         return dict(nx=o.nx, ny=o.ny, y_shift=o.y_shift, precision=o.precision, dx=o.dx, dt=o.dt,
                     eps_rr=o.eps_rr, w_ref=o.w_ref, capacity=o.capacity,
                     n_init=(o.n_init[0], o.n_init[1]), step=o.step, tile=o.tile,
-                    lds_slots=o.lds_slots)
+                    lds_slots=o.lds_slots,
+                    field_kernel={1: "tiles", 2: "strips"}.get(o.field_kernel, o.field_kernel),
+                    field_blocks=o.field_blocks)
 
     def diag(self) -> dict:
         o = N.PicDiagOut()

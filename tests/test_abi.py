@@ -115,6 +115,18 @@ def test_2d_config_validation_on_host():
                 dict(waist=-1.0), dict(cells_per_lambda=2)):
         c = make_config(preset2d("d1", **bad))
         assert lib.pic2d_workspace_bytes(C.byref(c), C.byref(n)) == N.PIC_EINVAL, bad
+    # field kernel choice: unknown values, and column strips over a period
+    # longer than one work-group (1,024 rows in FP32, 512 in FP64)
+    c = make_config(preset2d("d1"))
+    c.field_kernel = 3
+    assert lib.pic2d_workspace_bytes(C.byref(c), C.byref(n)) == N.PIC_EINVAL
+    for prec, rows, ok in (("fp32", 1024, True), ("fp32", 1056, False), ("fp64", 512, True),
+                           ("fp64", 544, False)):
+        c = make_config(preset2d("d1", precision=prec, box_y=rows / 32, field_kernel="strips"))
+        want = N.PIC_OK if ok else N.PIC_EINVAL
+        assert lib.pic2d_workspace_bytes(C.byref(c), C.byref(n)) == want, (prec, rows)
+        c = make_config(preset2d("d1", precision=prec, box_y=rows / 32))  # automatic: any period
+        assert lib.pic2d_workspace_bytes(C.byref(c), C.byref(n)) == N.PIC_OK
     c = make_config(preset2d("d1"))
     c.struct_size = C.sizeof(N.Pic2dConfig) - 8
     assert lib.pic2d_workspace_bytes(C.byref(c), C.byref(n)) == N.PIC_EINVAL

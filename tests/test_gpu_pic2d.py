@@ -212,10 +212,16 @@ def test_push_currents_conserve_charge_exactly():
 
 
 # --------------------------------------------------------------------------- fields
-@pytest.mark.parametrize("pol,waist,box_y", [("LP", 0.6, 1.0), ("CP", 0.0, 1.0),
-                                             ("CP", 0.3, 37 / 32)])  # 37 rows: partial tiles
-def test_field_advance_matches_oracle(pol, waist, box_y):
-    cfg = preset2d("d1", box_x=3.0, box_y=box_y, x_foil=1.0, pol=pol, waist=waist, a0=300.0)
+@pytest.mark.parametrize("kernel", ["tiles", "strips"])
+@pytest.mark.parametrize("pol,waist,box_y,box_x,precision", [
+    ("LP", 0.6, 1.0, 3.0, "fp32"), ("CP", 0.0, 1.0, 3.0, "fp32"),
+    ("CP", 0.3, 37 / 32, 3.0, "fp32"),  # 37 rows: partial tiles, a partial wave of rows
+    ("LP", 4.0, 32.0, 1.0, "fp32"),     # 1,024 rows: the longest period of one FP32 strip
+    ("CP", 2.0, 16.0, 2.0, "fp64"),     # 512 rows: the longest FP64 strip
+    ("LP", 0.3, 3 / 32, 2.0, "fp64")])  # 3 rows
+def test_field_advance_matches_oracle(kernel, pol, waist, box_y, box_x, precision):
+    cfg = preset2d("d1", box_x=box_x, box_y=box_y, x_foil=0.5, thickness=0.5, pol=pol, waist=waist,
+                   a0=300.0, precision=precision, field_kernel=kernel)
     sim = _oracle(cfg)
     nx, ny = sim.nx, sim.ny
     f = random_fields2d(7, nx, ny, 50.0)
@@ -238,10 +244,12 @@ def test_field_advance_matches_oracle(pol, waist, box_y):
     sim.advance_fields(Jx * s / (sim.dx * sim.dt), Jy * s / (sim.dx * sim.dt),
                        Jz * s / (sim.dx * sim.dx))
     assert st["step"] == step + 1
+    assert run.get_info()["field_kernel"] == kernel
+    tol = 1e-6 if precision == "fp32" else 1e-12
     for k in ("Ex", "Ey", "Ez", "Bx", "By", "Bz"):
         ref = getattr(sim, k)
         d = np.max(np.abs(st[k].astype(np.float64) - ref))
-        assert d <= 1e-6 * max(np.max(np.abs(ref)), 50.0), (k, d)
+        assert d <= tol * max(np.max(np.abs(ref)), 50.0), (k, d)
     # the running charge took exactly the divergence of the current
     div = contract2d.divergence(Jx, Jy)[1:nx + 2]
     assert np.array_equal(st["charge_int"], q0 - div)
@@ -273,9 +281,10 @@ def test_sort_orders_by_cell_and_keeps_every_particle():
 
 
 # --------------------------------------------------------------------------- whole runs
-@pytest.mark.parametrize("precision", ["fp32", "fp64"])
-def test_laser_foil_run_matches_oracle_budget(precision):
-    cfg = preset2d("d1", precision=precision)
+@pytest.mark.parametrize("precision,kernel", [("fp32", "strips"), ("fp64", "strips"),
+                                              ("fp32", "tiles")])
+def test_laser_foil_run_matches_oracle_budget(precision, kernel):
+    cfg = preset2d("d1", precision=precision, field_kernel=kernel)
     sim = opic2d.Pic2D(cfg)
     steps = 384  # 6 periods: the pulse (3 + 3 periods) reaches the foil at 4
     run = _run(cfg)

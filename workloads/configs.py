@@ -106,6 +106,7 @@ _BASE_2D = dict(
     jitter=0.5,
     periods=8.0,
     sort_interval=16,
+    field_kernel="auto",  # HIP field advance: "auto", "tiles" or "strips" (the oracle has one)
 )
 
 PRESETS_2D = {
