@@ -7,7 +7,8 @@ expected value comes from ``oracle``.  Tolerances:
   deposition contract);
 * one FP32 momentum step: relative error <= 1e-5 of the step's scale
   max(|u_old|, |u_L|, |u_new|, |dt q E / m|, |RR increment|, 1e-2); FP64 1e-12;
-* one field step: 1e-6 of the field scale (FP32 rounding of the update);
+* one field step (both field kernels, tiles and column strips): 1e-6 of the
+  field scale in FP32 (rounding of the update), 1e-12 in FP64;
 * whole runs: each energy term within 1e-3 of the injected energy.
 """
 import numpy as np
