@@ -50,7 +50,12 @@
  *     co-located; weight n0 dx dy / (ppc_x ppc_y).
  *
  * Cell index of a particle (state I/O): cell = ix * 2^y_shift + iy with
- * y_shift = ceil(log2 ny) (pic2d_info).  Grid arrays (state I/O) are
+ * y_shift = ceil(log2 ny) (pic2d_info).  The cell sort (pic2d_sort, and
+ * every sort_interval steps) orders particles by blocks of 8 x min(8,
+ * 2^y_shift) cells (pic2d_info's sort block shifts): blocks column by
+ * column (bx = ix >> sx, by = iy >> sy; by fastest), the cells of a block
+ * column by column, so that the particles of a push tile lie in a compact
+ * patch of the grid.  The order of particles within a cell is unspecified.  Grid arrays (state I/O) are
  * y-fastest: element (column, row) at column * ny + row, with nx + 1
  * columns for node components, nx + 2 for half-node components, nx + 2
  * for Jx_int, nx + 3 for Jy_int and Jz_int (column = node + 1), nx + 1 for
@@ -111,6 +116,8 @@ typedef struct pic2d_info {
   int32_t lds_slots;         /* 64-bit LDS current accumulators per push work-group */
   int32_t field_kernel;      /* the field advance in use: PIC2D_FIELD_TILES or _STRIPS */
   int32_t field_blocks;      /* its work-groups per launch */
+  int32_t sort_block_x_shift, sort_block_y_shift; /* sort order: blocks of 2^sx x 2^sy cells */
+  int32_t reserved_info;
 } pic2d_info;
 
 /* Particle arrays for state I/O: as pic_species_state, with two offsets. */

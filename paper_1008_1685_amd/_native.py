@@ -174,6 +174,9 @@ class Pic2dInfo(C.Structure):
         ("lds_slots", C.c_int32),
         ("field_kernel", C.c_int32),
         ("field_blocks", C.c_int32),
+        ("sort_block_x_shift", C.c_int32),
+        ("sort_block_y_shift", C.c_int32),
+        ("reserved_info", C.c_int32),
     ]
 
 

@@ -983,7 +983,20 @@ struct SortArgs {
   int nx;
   int comp;             // carry residuals of species 0
   int* pred;            // [2] the push's range-prediction flags, cleared: the order changes
+  int ysh, bxs, bys;    // 2D grids: cell = ix << ysh | iy, sorted by blocks of 2^bxs x 2^bys cells
 };
+
+// Sort key of a 2D cell: blocks of 2^bxs x 2^bys cells column by column,
+// and the cells of a block column by column, so that the particles of a
+// sort tile (and of a push tile) lie in a compact patch of the grid rather
+// than along one column.  A bijection of [0, roundup(nx, 2^bxs) << ysh);
+// with bxs = bys = 0 the key is the cell index itself.
+__device__ __forceinline__ int sort_key2(int c, int ysh, int bxs, int bys) {
+  if (c == kDead) return kDead;
+  const int ix = c >> ysh, iy = c & ((1 << ysh) - 1);
+  return ((ix >> bxs) << (ysh + bxs)) | ((iy >> bys) << (bxs + bys)) |
+         ((ix & ((1 << bxs) - 1)) << bys) | (iy & ((1 << bys) - 1));
+}
 
 constexpr int kSortThreads = 256;
 constexpr int kSortPPT = 8;                        // particles per thread per sort tile
@@ -1033,7 +1046,7 @@ __device__ __forceinline__ void tile_range(const int* cl, int& lo, int& hi, int*
 
 // per-cell particle counts: LDS histogram over the tile's cell window,
 // then one global atomic per occupied cell and tile
-template <typename R>
+template <typename R, bool KEY2 = false>
 __device__ __forceinline__ void sort_hist_block(const SortArgs<R>& p, int blk) {
   __shared__ int cnt[kSortWin];
   __shared__ int sm[8];
@@ -1047,6 +1060,7 @@ __device__ __forceinline__ void sort_hist_block(const SortArgs<R>& p, int blk) {
   for (int k = 0; k < kSortPPT; ++k) {
     const long long i = base + k * kSortThreads + threadIdx.x;
     cl[k] = i < n ? p.src[s].cell[i] : kDead;
+    if constexpr (KEY2) cl[k] = sort_key2(cl[k], p.ysh, p.bxs, p.bys);
   }
   int lo, hi;
   tile_range(cl, lo, hi, sm);
@@ -1191,25 +1205,32 @@ __device__ __forceinline__ void sort_scatter_block(const SortArgs<R>& p, int blk
       }
     }
   }
+  // bucket keys: the cell itself, or its 2D block key (OY)
+  int ky[kSortPPT];
+#pragma unroll
+  for (int k = 0; k < kSortPPT; ++k) {
+    if constexpr (OY) ky[k] = sort_key2(cl[k], p.ysh, p.bxs, p.bys);
+    else ky[k] = cl[k];
+  }
   int lo, hi;
-  tile_range(cl, lo, hi, sm);
+  tile_range(ky, lo, hi, sm);
   if (lo > hi) return;
   const int W = hi - lo + 1;
   if (W <= kSortWin) {
     for (int e = threadIdx.x; e < W; e += kSortThreads) cnt[e] = 0;
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < kSortPPT; ++k) pos[k] = wave_claim(cnt, cl[k] - lo, cl[k] != kDead);
+    for (int k = 0; k < kSortPPT; ++k) pos[k] = wave_claim(cnt, ky[k] - lo, ky[k] != kDead);
     __syncthreads();
     for (int e = threadIdx.x; e < W; e += kSortThreads)
       cnt[e] = cnt[e] ? atomicAdd(p.cursor[s] + lo + e, cnt[e]) : 0;
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kSortPPT; ++k)
-      if (cl[k] != kDead) pos[k] += cnt[cl[k] - lo];
+      if (ky[k] != kDead) pos[k] += cnt[ky[k] - lo];
   } else {
 #pragma unroll
-    for (int k = 0; k < kSortPPT; ++k) pos[k] = wave_claim(p.cursor[s], cl[k], cl[k] != kDead);
+    for (int k = 0; k < kSortPPT; ++k) pos[k] = wave_claim(p.cursor[s], ky[k], ky[k] != kDead);
   }
 #pragma unroll
   for (int k = 0; k < kSortPPT; ++k) {

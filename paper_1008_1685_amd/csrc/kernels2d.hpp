@@ -24,8 +24,9 @@
 // The cell sort reuses the 1D kernels (the y offset moves with the particle).
 //
 // Cell key of a particle: ix << ysh | iy (ysh = bits of ny rounded up to a
-// power of two), so that (ix, iy) decode with a shift and a mask and the
-// counting sort orders particles column by column, rows fastest.  Grid
+// power of two), so that (ix, iy) decode with a shift and a mask.  The
+// counting sort orders particles by blocks of 8 x 8 cells (sort_key2), so
+// that a push tile covers a compact patch of cells.  Grid
 // arrays are y-fastest with stride ny: component at (column X, row j) is
 // element X * ny + j.
 #pragma once
@@ -37,10 +38,14 @@ namespace pic {
 #ifndef PIC2D_PUSH_PPT
 #define PIC2D_PUSH_PPT 4
 #endif
+#ifndef PIC2D_SORT_BLOCK
+#define PIC2D_SORT_BLOCK 3
+#endif
 #ifndef PIC2D_LDS_SLOTS
 #define PIC2D_LDS_SLOTS 3072
 #endif
 
+constexpr int k2SortBlock = PIC2D_SORT_BLOCK;  // log2 of the sort blocks' side in cells
 constexpr int k2Q = 12;                   // fixed-point bits of a shape weight
 constexpr int k2One = 1 << k2Q;
 constexpr int k2PPT = PIC2D_PUSH_PPT;     // particles per thread per tile
@@ -669,6 +674,11 @@ __global__ __launch_bounds__(kScanThreads) void k_scan2_offsets(int* cur0, int* 
 }
 
 // cell sort of 2D particles: the 1D passes, with the y offset moved too
+template <typename R>
+__global__ __launch_bounds__(kSortThreads) void k_sort_hist2(SortArgs<R> p) {
+  sort_hist_block<R, true>(p, (int)blockIdx.x);
+}
+
 template <typename R>
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter2(SortArgs<R> p) {
   sort_scatter_block<R, true>(p, (int)blockIdx.x);

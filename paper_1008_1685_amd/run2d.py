@@ -100,7 +100,8 @@ class Run2D:
                     n_init=(o.n_init[0], o.n_init[1]), step=o.step, tile=o.tile,
                     lds_slots=o.lds_slots,
                     field_kernel={1: "tiles", 2: "strips"}.get(o.field_kernel, o.field_kernel),
-                    field_blocks=o.field_blocks)
+                    field_blocks=o.field_blocks, sort_block_shift=(o.sort_block_x_shift,
+                                                                   o.sort_block_y_shift))
 
     def diag(self) -> dict:
         o = N.PicDiagOut()

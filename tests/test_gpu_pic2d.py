@@ -261,7 +261,7 @@ def test_field_advance_matches_oracle(kernel, pol, waist, box_y, box_x, precisio
 
 
 # --------------------------------------------------------------------------- sort
-def test_sort_orders_by_cell_and_keeps_every_particle():
+def test_sort_orders_by_cell_block_and_keeps_every_particle():
     cfg = preset2d("d1", box_x=3.0, box_y=2.0, x_foil=1.0)
     sim = _oracle(cfg)
     nx, ny = sim.nx, sim.ny
@@ -273,7 +273,15 @@ def test_sort_orders_by_cell_and_keeps_every_particle():
     st = run.get_state()
     for s in range(2):
         a, b = before[f"sp{s}"], st[f"sp{s}"]
-        assert np.all(np.diff(b["cell"]) >= 0)
+        # blocks of 2^sx x 2^sy cells, blocks and the cells of a block column
+        # by column (include/pic2d.h)
+        sx, sy = run.get_info()["sort_block_shift"]
+        assert (sx, sy) == (3, 3)
+        ysh = run.get_info()["y_shift"]
+        ix, iy = b["cell"] >> ysh, b["cell"] & ((1 << ysh) - 1)
+        # sorted iff the stable lexicographic sort by (block x, block y, x, y) keeps the order
+        order = np.lexsort((iy, ix, iy >> sy, ix >> sx))
+        assert np.array_equal(order, np.arange(ix.size))
         ka = np.lexsort((a["ux"], a["oy"], a["ox"], a["cell"]))
         kb = np.lexsort((b["ux"], b["oy"], b["ox"], b["cell"]))
         for k in ("cell", "ox", "oy", "ux", "uy", "uz", "w"):
