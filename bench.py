@@ -138,8 +138,8 @@ def time_run_2d(cfg, steps, warmup, timing=TIMING_PERIOD):
 def bench_2d(warmup=1280, steps=400, side_runs=True, traffic_json=None):
     """The 2D3V form (2,560 x 1,024 cells, 8.4e6 particles, LP a0 = 500 with
     a 4-wavelength waist), timed from the pulse's arrival at the foil: one
-    step = push-deposit, the three field launches, the cell sort every 16
-    steps.  The push kernel's roofline is reported as for the 1D path."""
+    step = push-deposit, the field advance, the cell sort every 24 steps.
+    The push kernel's roofline is reported as for the 1D path."""
     from workloads import preset2d
 
     cfg = preset2d("d2")

@@ -116,7 +116,7 @@ PRESETS_2D = {
     # 8.4e6 particles (64 per cell per species), LP a0=500, 4-wavelength waist
     "d2": dict(_BASE_2D, cells_per_lambda=64, box_x=40.0, box_y=16.0, a0=500.0, waist=4.0,
                t_rise=5.0, t_fall=5.0, n0=100.0, x_foil=10.0, ppc_x=8, ppc_y=8,
-               periods=20.0),
+               periods=20.0, sort_interval=24),
 }
 
 
