@@ -57,7 +57,10 @@ constexpr int kLdsSlots = PIC_PUSH_LDS_SLOTS;  // 64-bit LDS current accumulator
 constexpr int kDepth = PIC_PUSH_DEPTH;        // particles per thread whose loads are in flight
 constexpr int kRingUnroll = PIC_RING_UNROLL;  // ring turns per loop iteration (renames, no copies)
 constexpr int kLanes = 64;            // wavefront width
-constexpr int kFieldChunk = 256;      // nodes per field work-group
+#ifndef PIC_FIELD_CHUNK
+#define PIC_FIELD_CHUNK 64
+#endif
+constexpr int kFieldChunk = PIC_FIELD_CHUNK;  // nodes per field work-group
 constexpr int kTwo24 = 1 << 24;
 
 template <typename R>
