@@ -177,7 +177,7 @@ pic_status pic2d_get_state(struct pic2d_run* run, pic2d_state* st, void* stream)
 pic_status pic2d_set_state(struct pic2d_run* run, const pic2d_state* st, void* stream);
 
 /* Per-kernel timing as pic_timing_enable / pic_timing_read (kinds 0 push,
- * 1 field advance: its three launches, 2 sort). */
+ * 1 field advance, 2 sort: its four launches). */
 pic_status pic2d_timing_enable(struct pic2d_run* run, int32_t period);
 pic_status pic2d_timing_read(struct pic2d_run* run, double ms[3], int64_t launches[3], void* stream);
 
