@@ -219,9 +219,11 @@ def test_push_currents_conserve_charge_exactly():
     ("CP", 0.3, 37 / 32, 3.0, "fp32"),  # 37 rows: partial tiles, a partial wave of rows
     ("LP", 4.0, 32.0, 1.0, "fp32"),     # 1,024 rows: the longest period of one FP32 strip
     ("CP", 2.0, 16.0, 2.0, "fp64"),     # 512 rows: the longest FP64 strip
-    ("LP", 0.3, 3 / 32, 2.0, "fp64")])  # 3 rows
+    ("LP", 0.3, 3 / 32, 2.0, "fp64"),   # 3 rows
+    ("CP", 0.2, 1.0, 0.25, "fp32")])    # 8 cells: strips of 3-4 columns, narrower than their halos
 def test_field_advance_matches_oracle(kernel, pol, waist, box_y, box_x, precision):
-    cfg = preset2d("d1", box_x=box_x, box_y=box_y, x_foil=0.5, thickness=0.5, pol=pol, waist=waist,
+    foil = min(0.5, box_x / 4)
+    cfg = preset2d("d1", box_x=box_x, box_y=box_y, x_foil=foil, thickness=foil, pol=pol, waist=waist,
                    a0=300.0, precision=precision, field_kernel=kernel)
     sim = _oracle(cfg)
     nx, ny = sim.nx, sim.ny
