@@ -553,10 +553,33 @@ __device__ __forceinline__ PData<R> load_particle(const SpeciesDev<R>& sp, int i
   return d;
 }
 
-// One particle: gather, Boris, RR, move, deposit, store.
+// The four field loads of one particle's gather: (E_y, E_z) at the nodes
+// either side and (E_x, B_y, B_z) at the half-nodes either side.  They are
+// issued from the particle's ring entry one particle ahead of its push, so
+// that their latency overlaps the push of the particle before it.
+template <typename R>
+struct Gath {
+  NodeF<R> n0, n1;
+  HalfF<R> h0, h1;
+};
+
+template <typename R>
+__device__ __forceinline__ Gath<R> gather_issue(const FieldsDev<R>& f, const PData<R>& pd) {
+  const unsigned uc = pd.c == kDead ? 0u : (unsigned)pd.c;  // removed: any valid address
+  const unsigned h = uc + (pd.o + R(0.5) >= R(1));
+  Gath<R> g;
+  g.n0 = ld(f.N, uc);
+  g.n1 = ld(f.N, uc + 1);
+  g.h0 = ld(f.H, h);
+  g.h1 = ld(f.H, h + 1);
+  return g;
+}
+
+// One particle: gather (from its field loads issued ahead), Boris, RR, move,
+// deposit, store.
 template <typename R, bool RR, bool COMP>
 __device__ __forceinline__ void push_particle(const PushArgs<R>& a, const SpeciesDev<R>& sp,
-                                              int s, int i, const PData<R>& pd,
+                                              int s, int i, const PData<R>& pd, const Gath<R>& gf,
                                               DepositCtx& dc, PushAcc& acc) {
   const int c = pd.c;
   if (c == kDead) return;
@@ -564,21 +587,23 @@ __device__ __forceinline__ void push_particle(const PushArgs<R>& a, const Specie
   const R o = pd.o, ux = pd.ux, uy = pd.uy, uz = pd.uz, w = pd.w;
   float rx = pd.rx, ry = pd.ry, rz = pd.rz;
 
-  // ---- gather E^n, B^n (linear weights; E_y,E_z on nodes, the rest on half-nodes)
-  const unsigned uc = (unsigned)c;
+  // ---- gather E^n, B^n (linear weights; E_y,E_z on nodes, the rest on half-nodes).
+  // The fused multiply-adds are written out: left to contraction, the two
+  // unrolled ring slots were compiled with different roundings, and a
+  // particle's result then depended on its slot, which the sort's order
+  // within a cell leaves open.
   const R on = R(1) - o;
-  const NodeF<R> n0 = ld(a.f.N, uc), n1 = ld(a.f.N, uc + 1);
-  const R ey = on * n0.ey + o * n1.ey;
-  const R ez = on * n0.ez + o * n1.ez;
+  const NodeF<R> n0 = gf.n0, n1 = gf.n1;
+  const R ey = fma(o, n1.ey, on * n0.ey);
+  const R ez = fma(o, n1.ez, on * n0.ez);
   const R sx = o + R(0.5);
   const unsigned hb = sx >= R(1);
   const R fh = hb ? sx - R(1) : sx;
-  const unsigned h = uc + hb;
   const R fn = R(1) - fh;
-  const HalfF<R> h0 = ld(a.f.H, h), h1 = ld(a.f.H, h + 1);
-  const R ex = fn * h0.ex + fh * h1.ex;
-  const R by = fn * h0.by + fh * h1.by;
-  const R bz = fn * h0.bz + fh * h1.bz;
+  const HalfF<R> h0 = gf.h0, h1 = gf.h1;
+  const R ex = fma(fh, h1.ex, fn * h0.ex);
+  const R by = fma(fh, h1.by, fn * h0.by);
+  const R bz = fma(fh, h1.bz, fn * h0.bz);
 
   MomentumOut<R> mo;
   momentum_step<R, RR, COMP, false>(ux, uy, uz, ex, ey, ez, by, bz, a.qh[s], a.eps * a.dt,
@@ -702,15 +727,19 @@ __device__ __forceinline__ void push_tile(const PushArgs<R>& a, int s, int tile,
 
   PushAcc acc{0.f, 0.f, 0.f, INT_MAX, INT_MIN};
   // ring slot j holds particle k0 + j; its successor D ahead is loaded
-  // before particle k0 + j is computed
+  // before particle k0 + j is computed, and the field loads of particle
+  // k0 + j + 1 (whose ring entry has arrived) before those of k0 + j + D
+  Gath<R> gnext = gather_issue<R>(a.f, ring[0]);
 #pragma unroll kRingUnroll
   for (int k0 = 0; k0 < PPT; k0 += D) {
 #pragma unroll
     for (int j = 0; j < D; ++j) {
       const int i = base + (k0 + j) * kThreads + tid;
       const PData<R> cur = ring[j];
+      const Gath<R> gcur = gnext;
+      if (k0 + j + 1 < PPT) gnext = gather_issue<R>(a.f, ring[(j + 1) % D]);
       if (k0 + j + D < PPT) ring[j] = load_particle<R, COMP>(sp, i + D * kThreads, n);
-      push_particle<R, RR, COMP>(a, sp, s, i, cur, dc, acc);
+      push_particle<R, RR, COMP>(a, sp, s, i, cur, gcur, dc, acc);
     }
   }
 
