@@ -25,7 +25,7 @@
 namespace pic {
 
 #ifndef PIC_PUSH_PPT
-#define PIC_PUSH_PPT 16
+#define PIC_PUSH_PPT 20
 #endif
 #ifndef PIC_BATCH_PPT
 #define PIC_BATCH_PPT 4
@@ -34,7 +34,7 @@ namespace pic {
 #define PIC_PUSH_LDS_SLOTS 3072
 #endif
 #ifndef PIC_PUSH_DEPTH
-#define PIC_PUSH_DEPTH 2
+#define PIC_PUSH_DEPTH 4
 #endif
 #ifndef PIC_RING_UNROLL
 #define PIC_RING_UNROLL 2
