@@ -108,7 +108,9 @@ typedef struct pic_info {
   int64_t capacity;          /* per species */
   int64_t n_init[2];         /* particles per species after pic_init */
   int64_t step;              /* steps enqueued so far */
-  int32_t tile;              /* particles per push work-group of a single run (batched steps use 1024) */
+  int32_t tile;              /* particles per push work-group of a single run: 5120, or 1024 when
+                                the foil gives fewer than two 5120-particle tiles per compute unit
+                                (chosen at pic_init; batched steps use 1024) */
   int32_t lds_slots;         /* 64-bit LDS current accumulators per push work-group */
 } pic_info;
 

@@ -826,6 +826,14 @@ __global__ PIC_PUSH_BOUNDS void k_push(PushArgs<R> a) {
   push_one_tile<R, kPPT, kDepth>(a, (int)blockIdx.x, lds);
 }
 
+// the same push in tiles of kBatchTile (the whole tile's loads up front),
+// for runs too small to fill the device with kTile tiles
+template <typename R>
+__global__ PIC_PUSH_BOUNDS void k_push_small(PushArgs<R> a) {
+  __shared__ unsigned long long lds[kLdsSlots];
+  push_one_tile<R, kBatchPPT, kBatchPPT>(a, (int)blockIdx.x, lds);
+}
+
 // ---------------------------------------------------------------- fields
 template <typename R>
 struct FieldArgs {
