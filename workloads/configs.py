@@ -51,7 +51,7 @@ PRESETS = {
     # (the cell sort every 32 steps: the push is as fast as with 16, the sort
     # costs half as much per step)
     "c3": dict(_BASE, cells_per_lambda=200, box_lambda=100.0, pol="LP", a0=500.0,
-               n0=100.0, ppc=25000, periods=80.0, sort_interval=32),
+               n0=100.0, ppc=25000, periods=80.0, sort_interval=64),
     # stress case: 80,000 cells, 2e8 particles, RR-dominated
     "c5": dict(_BASE, cells_per_lambda=400, box_lambda=200.0, pol="LP", a0=800.0,
                n0=100.0, thickness=2.0, ppc=125000, periods=150.0, sort_interval=32),
