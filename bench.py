@@ -7,9 +7,22 @@ energy budget and Gauss check.  Prints one JSON line.
 Workload (default): laser-foil run at the precision-form scale - LP a0 = 500,
 200 cells per wavelength, 100 wavelengths (20,000 cells), hydrogen foil of
 1 wavelength at n0 = 100 n_c with 25,000 particles per cell per species
-(1e7 particles), FP32 particles with compensated RR, FP64 reductions.  The
-warm-up steps carry the run into the laser-foil interaction (the pulse
-reaches the foil after 8 periods = 3,200 steps) before timing starts.
+(1e7 particles), FP32 particles with compensated RR, FP64 reductions.
+
+Timed window.  Every timed run is first stepped, untimed, to 10 laser
+periods (4,000 steps; the pulse reaches the foil after 8 periods), so the
+window lies inside the laser-foil interaction whatever --steps and --warmup
+are; --warmup adds steps on top.  The cell sort runs every I steps (I = 64),
+and a sort costs more than its own kernel: the push after it has no cell
+ranges from the previous push and scans its tiles first.  The headline
+window therefore charges the sort at its configured rate, 1/I per step,
+from the same run: with s0 the first sort step after the lead-in and
+m = I/2, the wall time of the m steps [s0 - m, s0) (no sort) and of the m
+steps [s0, s0 + m) (one sort) give the cost of one sort, C; the K timed steps
+[s0 + m, s0 + m + K) hold n sorts; the time per step is
+(wall - n C + (K/I) C) / K.  The raw wall time is reported beside it.  Side
+runs time whole sort intervals that open with a sort, which hold the
+configured share of sorts by themselves.
 """
 from __future__ import annotations
 
@@ -66,14 +79,55 @@ def alg_bytes_per_push(precision: str, compensated: bool, rr: bool):
     return ele, ion
 
 
-def time_run(cfg, steps, warmup, diag_every, timing=TIMING_PERIOD):
+# untimed lead-in of every timed run: into the laser-foil interaction
+T_START_PERIODS = 10.0
+
+
+def window_start(cfg, warmup, t_start=T_START_PERIODS):
+    """First timed step: t_start periods plus `warmup` steps, rounded up to a
+    step at which the cell sort runs (multiples of the sort interval)."""
+    from workloads import periods_to_steps
+
+    lead = periods_to_steps(dict(cfg, periods=t_start)) + max(int(warmup), 0)
+    k = cfg["sort_interval"]
+    return -(-lead // k) * k
+
+
+def time_run(cfg, steps, warmup, diag_every, timing=TIMING_PERIOD, t_start=T_START_PERIODS,
+             keep_state=False, sort_cost=False):
+    """Time `steps` steps of `cfg` after the lead-in to t_start periods plus
+    `warmup` steps.  sort_cost=False: the window opens at a sort step and its
+    wall time is taken as is.  sort_cost=True: the sort is charged at
+    1/sort_interval per step with its cost measured in the same run (the
+    module docstring)."""
     import torch
 
     from paper_1008_1685_amd import Run
 
     run = Run(cfg)
-    run.step(warmup)
+    interval = cfg["sort_interval"]
+    s0 = window_start(cfg, warmup, t_start)
+    m = max(interval // 2, 1)
+
+    def wall(k):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        run.step(k)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t
+
+    if sort_cost:
+        run.step(s0 - m)
+        t_plain = wall(m)   # [s0 - m, s0): no sort
+        t_sort = wall(m)    # [s0, s0 + m): the sort at s0 and the push after it
+        c_sort = max(t_sort - t_plain, 0.0)
+        start = s0 + m
+    else:
+        run.step(s0)
+        c_sort = None
+        start = s0
     d0 = run.diag()
+    state = run.get_state() if keep_state else None
     torch.cuda.synchronize()
     run.timing(timing)
     t0 = time.perf_counter()
@@ -91,12 +145,21 @@ def time_run(cfg, steps, warmup, diag_every, timing=TIMING_PERIOD):
     d1 = run.diag()
     n_e = 0.5 * (d0["n_alive"][0] + d1["n_alive"][0])
     n_i = 0.5 * (d0["n_alive"][1] + d1["n_alive"][1])
-    out = dict(seconds=t1 - t0, n_e=n_e, n_i=n_i, kernels=kt, diag0=d0, diag1=d1,
-               info=run.get_info())
+    # sort steps inside [start, start + steps)
+    sorts = (start + steps - 1) // interval - (start - 1) // interval
+    raw = t1 - t0
+    seconds = raw if c_sort is None else raw - sorts * c_sort + steps / interval * c_sort
+    out = dict(seconds=seconds, raw_seconds=raw, sorts_in_window=sorts, sort_cost_s=c_sort,
+               start=start, n_e=n_e, n_i=n_i, kernels=kt, diag0=d0, diag1=d1,
+               info=run.get_info(), state=state)
     run.close()
     del run
     torch.cuda.empty_cache()
     return out
+
+
+def pushes_per_s(r, steps):
+    return (r["n_e"] + r["n_i"]) * steps / r["seconds"]
 
 
 def alg_bytes_per_push_2d(precision: str, compensated: bool, rr: bool):
@@ -185,29 +248,45 @@ def side_by_side_c2(warmup=3200, steps=2000):
     for prec in ("fp64", "fp32"):
         for rr in (True, False):
             cfg = preset("c2", precision=prec, rr=rr)
-            r = time_run(cfg, steps, warmup, steps, timing=0)
-            out[f"{prec}_rr_{'on' if rr else 'off'}"] = (r["n_e"] + r["n_i"]) * steps / r["seconds"]
+            r = time_run(cfg, steps, warmup, steps, t_start=0.0)
+            out[f"{prec}_rr_{'on' if rr else 'off'}"] = pushes_per_s(r, steps)
     out["speedup_fp32_over_fp64"] = out["fp32_rr_on"] / out["fp64_rr_on"]
     out["rr_overhead_fp64"] = out["fp64_rr_off"] / out["fp64_rr_on"] - 1.0
     out["workload"] = "c2: LP a0=300, 12000 cells, 400000 particles, steps 3200-5200, pushes/s"
     return out
 
 
-def cpu_baseline(cfg, budget_s=20.0, max_steps=8):
-    """The FP64 oracle, as is, on a bounded sample of the same workload."""
+def cpu_baseline(cfg, state, budget_s=20.0, max_steps=12):
+    """The FP64 oracle, as is, on a bounded sample of the same workload: a few
+    steps from the state at which the GPU's timed window starts (particles,
+    fields and the laser clock taken from the GPU run, promoted to FP64)."""
+    import numpy as np
+
     from oracle import pic as opic
 
-    sim = opic.Pic1D(cfg)
+    sim = opic.Pic1D(cfg, init_particles=False)
+    for k in ("Ex", "Ey", "Ez", "By", "Bz"):
+        getattr(sim, k)[:] = np.asarray(state[k], dtype=np.float64)
+    for s in range(2):
+        p = state[f"sp{s}"]
+        u = np.stack([np.asarray(p[k], np.float64) for k in ("ux", "uy", "uz")], 1)
+        sim.set_particles(s, p["cell"], p["off"], u, p["w"])
+    sim.step_n = int(state["step"])
     n = sim.sp[0]["xi"].size + sim.sp[1]["xi"].size
     t0 = time.perf_counter()
     k = 0
+    pushes = 0
     while k < max_steps and (time.perf_counter() - t0) < budget_s:
+        pushes += sim.sp[0]["xi"].size + sim.sp[1]["xi"].size
         sim.step()
         k += 1
     dt = time.perf_counter() - t0
-    return dict(value=n * k / dt, unit="pushes/s", cores=1, kind="oracle",
-                sample=f"{k} oracle steps of the same workload from its initial state "
-                       f"({n} particles; numpy, single thread)")
+    t_p = int(state["step"]) * sim.dt / (2.0 * 3.141592653589793)
+    return dict(value=pushes / dt, unit="pushes/s", cores=1, host_cpu_count=os.cpu_count(),
+                kind="oracle",
+                sample=f"{k} oracle steps ({pushes} pushes, {dt:.1f} s) from the GPU run's state at "
+                       f"step {int(state['step'])} (t = {t_p:.2f} periods, {n} particles), "
+                       "where the timed window starts; numpy, one thread")
 
 
 def serve_bench(n_runs=256, rate=20.0, seed=0, max_slots=64, budget_gb=64.0):
@@ -239,7 +318,7 @@ def serve_bench(n_runs=256, rate=20.0, seed=0, max_slots=64, budget_gb=64.0):
                 peak_resident_bytes=srv.peak_bytes, max_slots=max_slots, failed_checks=bad)
 
 
-def stress_bench(serve_kwargs, warm=400, window=200, chunk=8, share=0.2):
+def stress_bench(serve_kwargs, t_start=8.5, window=200, chunk=8, share=0.2):
     """The stress run (2e8 particles, 80,000 cells, LP a0 = 800) on its own
     stream: its throughput alone, then stepped by a second host thread while
     the serving stream is served on the same GPU (latency under load).  Both
@@ -258,6 +337,7 @@ def stress_bench(serve_kwargs, warm=400, window=200, chunk=8, share=0.2):
     st = torch.cuda.Stream()
     run = Run(cfg, stream=st)
     n = sum(run.get_info()["n_init"])
+    warm = window_start(cfg, 0, t_start)  # the pulse reaches the foil after 8 periods
     run.step(warm)
     st.synchronize()
     t0 = time.perf_counter()
@@ -288,7 +368,8 @@ def stress_bench(serve_kwargs, warm=400, window=200, chunk=8, share=0.2):
     d = run.diag()
     run.close()
     return dict(workload=f"c5: LP a0={cfg['a0']:g}, {run.info['n_init'][0] + run.info['n_init'][1]} particles, "
-                         f"80000 cells, fp32 + compensated RR, stepped from step {warm}",
+                         f"80000 cells, fp32 + compensated RR, stepped from step {warm} "
+                         f"({warm / 800:.2f} periods, in the laser-foil interaction)",
                 pushes_per_s_alone=alone, duty_cycle=share, pushes_per_s_with_serving=n * done[0] / el,
                 steps_with_serving=done[0], gauss_int=d["gauss_int"],
                 serving_under_load=serving)
@@ -328,7 +409,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=4000)
-    ap.add_argument("--warmup", type=int, default=4000)
+    ap.add_argument("--warmup", type=int, default=0,
+                    help="steps on top of the untimed lead-in to 10 periods")
     ap.add_argument("--diag-every", type=int, default=1000)
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--no-side-runs", action="store_true",
@@ -383,9 +465,9 @@ def main():
               flush=True)
         return
     cfg = preset(args.workload)
-    res = time_run(cfg, args.steps, args.warmup, args.diag_every)
-    pushes = (res["n_e"] + res["n_i"]) * args.steps
-    value = pushes / res["seconds"]
+    res = time_run(cfg, args.steps, args.warmup, args.diag_every,
+                   keep_state=not args.no_side_runs, sort_cost=True)
+    value = pushes_per_s(res, args.steps)
     be, bi = alg_bytes_per_push(cfg["precision"], cfg["rr_compensated"], cfg["rr"])
     push_ms, push_n = res["kernels"]["push"]
     avg_push_s = push_ms * 1e-3 / max(push_n, 1)
@@ -407,8 +489,16 @@ def main():
                              f"{cfg['precision']} + compensated RR, FP64 budgets",
                     n_cells=res["info"]["n_cells"], particles=int(res["n_e"] + res["n_i"]),
                     sort_interval=cfg["sort_interval"], diag_every=args.diag_every,
-                    t_start_periods=args.warmup * res["info"]["dt"] / (2 * 3.141592653589793),
+                    t_start_periods=res["start"] * res["info"]["dt"] / (2 * 3.141592653589793),
+                    window_steps=[res["start"], res["start"] + args.steps],
                     parallelism="single GPU"),
+        window=dict(raw_ms_per_step=res["raw_seconds"] * 1e3 / args.steps,
+                    sorts_in_window=res["sorts_in_window"], sort_cost_ms=res["sort_cost_s"] * 1e3,
+                    method=f"time per step = (wall - {res['sorts_in_window']} C + steps/"
+                           f"{cfg['sort_interval']} C) / steps; C, the cost of one sort (its kernels "
+                           "and the push after it), is the wall time of the half interval that "
+                           "opens with the sort before the window minus that of the half interval "
+                           "before it, in the same run"),
         roofline=dict(bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s",
                       frac=achieved / PEAK_HBM_GBS, traffic=traffic,
                       kernel="k_push", bytes_per_launch=bytes_per_launch,
@@ -416,22 +506,39 @@ def main():
         kernel_us_per_launch={k: v[0] * 1e3 / max(v[1], 1) for k, v in res["kernels"].items()},
         kernel_ms_per_step={k: v[0] / max(v[1], 1) * (1.0 / cfg["sort_interval"] if k == "sort" else 1.0)
                             for k, v in res["kernels"].items()},
+        kernel_launches_timed={k: v[1] for k, v in res["kernels"].items()},
         timing=f"HIP start/end events of every {TIMING_PERIOD}th launch of each kernel",
         energy_balance=res["diag1"]["balance"] / max(res["diag1"]["E_in"], 1e-300),
         gauss_int=res["diag1"]["gauss_int"],
     )
     if not args.no_side_runs:
-        side = max(args.steps // 4, 200)
-        r_off = time_run(dict(cfg, rr=False), side, args.warmup, args.diag_every)
-        r_64 = time_run(dict(cfg, precision="fp64"), side, args.warmup, args.diag_every)
-        v_off = (r_off["n_e"] + r_off["n_i"]) * side / r_off["seconds"]
-        v_64 = (r_64["n_e"] + r_64["n_i"]) * side / r_64["seconds"]
-        line["rr_cost"] = dict(pushes_per_s_rr_off=v_off, overhead=v_off / value - 1.0,
+        # side runs over the same window (the same lead-in, at least 256 steps)
+        # (a whole number of sort intervals: the sorts in the window are the configured share)
+        side = max(-(-args.steps // cfg["sort_interval"]) * cfg["sort_interval"], 256)
+        r_on = time_run(cfg, side, args.warmup, args.diag_every, timing=0)
+        v_on = pushes_per_s(r_on, side)
+        r_off = time_run(dict(cfg, rr=False), side, args.warmup, args.diag_every, timing=0)
+        r_64 = time_run(dict(cfg, precision="fp64"), side, args.warmup, args.diag_every, timing=0)
+        v_off = pushes_per_s(r_off, side)
+        v_64 = pushes_per_s(r_64, side)
+        line["rr_cost"] = dict(pushes_per_s_rr_on=v_on, pushes_per_s_rr_off=v_off,
+                               overhead=v_off / v_on - 1.0, steps=side,
                                paper="about +10% compute time with RR (Section 3)")
-        line["fp64_path"] = dict(pushes_per_s=v_64, speedup_fp32_over_fp64=value / v_64)
+        line["fp64_path"] = dict(pushes_per_s=v_64, pushes_per_s_fp32=v_on,
+                                 speedup_fp32_over_fp64=v_on / v_64, steps=side)
+        # the other polarisation and amplitude of the precision-form workload
+        variants = {}
+        for pol, a0 in (("CP", 500.0), ("CP", 200.0), ("LP", 200.0)):
+            r_v = time_run(dict(cfg, pol=pol, a0=a0), side, args.warmup, args.diag_every, timing=0)
+            variants[f"{pol}_a0_{a0:g}"] = dict(pushes_per_s=pushes_per_s(r_v, side),
+                                                energy_balance=r_v["diag1"]["balance"] / r_v["diag1"]["E_in"],
+                                                gauss_int=r_v["diag1"]["gauss_int"])
+        variants["LP_a0_500"] = dict(pushes_per_s=v_on)
+        variants["steps"] = side
+        line["c3_variants"] = variants
         line["plain_method_scale"] = side_by_side_c2()
         line["pic2d"] = bench_2d()
-        line["cpu_baseline"] = cpu_baseline(cfg)
+        line["cpu_baseline"] = cpu_baseline(cfg, res["state"])
     if not args.no_serve:
         line["serving"] = serve_bench()
         if not args.no_stress:

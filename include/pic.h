@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define PIC_ABI_VERSION 1
+#define PIC_ABI_VERSION 2
 
 typedef enum pic_status {
   PIC_OK = 0,
@@ -115,9 +115,12 @@ typedef struct pic_info {
 } pic_info;
 
 /* Diagnostics at the current step n (particles at x^n with u^{n-1/2},
- * fields E^n, B^n).  Energies are in units of m^2 omega^2 c^2 / (4 pi e^2)
- * per unit transverse area (field: sum of field^2/2 dx; particle:
- * sum of w M (gamma - 1)); all reductions in FP64. */
+ * fields E^n, B^n): the energy balance of Section 2, in which the field and
+ * kinetic energies plus the energy radiated by the RR force (a loss, counted
+ * as it is emitted) and the energy that left the box account for the laser
+ * energy that entered it.  Energies are in units of
+ * m^2 omega^2 c^2 / (4 pi e^2) per unit transverse area (field: sum of
+ * field^2/2 dx; particle: sum of w M (gamma - 1)); all reductions in FP64. */
 typedef struct pic_diag_out {
   int64_t step;
   double t;
@@ -133,6 +136,9 @@ typedef struct pic_diag_out {
   int64_t n_stiff;           /* RR pushes with dt|f_R| > 0.1 |u_L| (cumulative) */
   int32_t nonfinite;         /* 1 if a NaN/Inf particle was seen */
   int32_t reserved;
+  double U_field;            /* U_Ex + U_Et + U_B */
+  double balance;            /* U_field + K_e + K_i + E_rad + E_out_left + E_out_right
+                                + E_esc - E_in (0 for exact conservation) */
 } pic_diag_out;
 
 /* Host-side particle and field state for pic_get_state / pic_set_state.
@@ -154,6 +160,18 @@ typedef struct pic_species_state {
   float* rx; float* ry; float* rz; /* [count] fp32 RR residuals (electrons) */
 } pic_species_state;
 
+/* Cumulative budget terms of a run (the time integrals of the energy
+ * balance above), carried by a checkpoint so that a resumed run continues
+ * its balance instead of restarting it from zero. */
+typedef struct pic_budget_state {
+  int32_t valid;             /* get: set to 1; set: 1 = replace the run's totals, 0 = keep them */
+  int32_t nonfinite;         /* the run's non-finite flag */
+  double E_in, E_out_left, E_out_right; /* energy through the boundaries */
+  double E_rad;              /* RR loss */
+  double E_esc[2];           /* kinetic energy of removed electrons, ions */
+  double n_stiff;            /* stiff RR pushes */
+} pic_budget_state;
+
 typedef struct pic_state {
   pic_species_state sp[2];
   void* Ex; void* Ey; void* Ez; void* By; void* Bz; /* real arrays, see above */
@@ -162,6 +180,7 @@ typedef struct pic_state {
   int64_t* Jy_int;           /* [n + 3] */
   int64_t* Jz_int;           /* [n + 3] */
   int64_t step;              /* step counter n (set: also sets the laser clock) */
+  pic_budget_state budget;   /* cumulative budget terms and the non-finite flag */
 } pic_state;
 
 /* Workspace bytes a run with `cfg` needs (host-only; no GPU access). */
@@ -206,10 +225,18 @@ pic_status pic_sort(struct pic_run* run, void* stream);
  * Particle arrays given to pic_get_state must hold `capacity` entries
  * (pic_get_info); removed particles are skipped, so counts are alive counts
  * (all particle arrays NULL: fields and currents only, count set to 0).
+ * pic_get_state always fills `budget` (valid = 1).
  * pic_set_state validates cells and offsets, replaces the particle arrays
  * (count <= capacity; the current buffers of both parities are cleared when
  * particles are replaced) and/or fields, Ex_int and the current buffers of
- * the current step; step >= 0 also resets the step counter. */
+ * the current step; step >= 0 also resets the step counter; budget.valid = 1
+ * replaces the cumulative budget terms and the non-finite flag.
+ * A state taken at step n and set into a fresh run of the same
+ * configuration continues as the original run would: particles, fields and
+ * integer currents, the boundary energies and every integer diagnostic
+ * repeat bit for bit; FP64 sums over particles (kinetic, radiated, escaped
+ * energy) agree to rounding, since their order follows the particle order
+ * within a cell, which the sort leaves open. */
 pic_status pic_get_state(struct pic_run* run, pic_state* st, void* stream);
 
 /* Raw read of particles first .. first + count - 1 of one species (0
@@ -316,9 +343,17 @@ pic_status pic_batch_create(int32_t precision, int32_t max_slots, int32_t quantu
 
 /* Admit a run at step 0 (fresh from pic_init) to be advanced to step
  * n_steps.  Its sort_interval must equal the quantum and its precision the
- * batch's.  PIC_EBUSY if no slot or work capacity is free.  Blocking. */
+ * batch's.  PIC_EBUSY if no slot or work capacity is free now; PIC_EINVAL
+ * if the run exceeds the capacity of an empty batch.  Blocking. */
 pic_status pic_batch_admit(pic_batch* b, struct pic_run* run, int64_t n_steps, void* stream,
                            int32_t* slot);
+
+/* Whether a run of configuration cfg would be admitted, before any device
+ * memory is set aside for it: *now = 1 if a slot and the work capacity are
+ * free at this moment, *ever = 1 if it fits an empty batch (0: it can never
+ * be admitted).  PIC_EINVAL for an invalid config or one whose precision or
+ * sort_interval the batch cannot take.  Host-only. */
+pic_status pic_batch_fits(const pic_batch* b, const pic_config* cfg, int32_t* now, int32_t* ever);
 
 /* Enqueue n_quanta graph replays (quantum steps each) for every resident
  * run; runs stop at their n_steps.  Async.  The first call captures the graph. */

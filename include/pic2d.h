@@ -137,6 +137,7 @@ typedef struct pic2d_state {
   int64_t* charge_int;       /* [(nx + 1) ny] running charge: initial charge minus the
                                 integrated divergence of the current */
   int64_t step;
+  pic_budget_state budget;   /* cumulative budget terms and the non-finite flag, as in pic.h */
 } pic2d_state;
 
 /* Workspace bytes (host-only). */
@@ -172,7 +173,11 @@ void pic2d_free(struct pic2d_run* run);
  * validates cells and offsets; replacing particles clears both current
  * buffers and restarts charge_int from the new particles' charge; fields,
  * currents and charge_int are written when given; step >= 0 resets the
- * step counter (and the laser clock). */
+ * step counter (and the laser clock); budget as in pic_get_state and
+ * pic_set_state (get always fills it; set with budget.valid = 1 replaces the
+ * run's cumulative terms).  A checkpoint set into a fresh run continues the
+ * run: state and integer diagnostics repeat bit for bit, FP64 sums to
+ * rounding. */
 pic_status pic2d_get_state(struct pic2d_run* run, pic2d_state* st, void* stream);
 pic_status pic2d_set_state(struct pic2d_run* run, const pic2d_state* st, void* stream);
 

@@ -84,7 +84,41 @@ class PicDiagOut(C.Structure):
         ("n_stiff", C.c_int64),
         ("nonfinite", C.c_int32),
         ("reserved", C.c_int32),
+        ("U_field", C.c_double),
+        ("balance", C.c_double),
     ]
+
+
+class PicBudgetState(C.Structure):
+    _fields_ = [
+        ("valid", C.c_int32),
+        ("nonfinite", C.c_int32),
+        ("E_in", C.c_double),
+        ("E_out_left", C.c_double),
+        ("E_out_right", C.c_double),
+        ("E_rad", C.c_double),
+        ("E_esc", C.c_double * 2),
+        ("n_stiff", C.c_double),
+    ]
+
+
+BUDGET_KEYS = ("nonfinite", "E_in", "E_out_left", "E_out_right", "E_rad", "E_esc", "n_stiff")
+
+
+def budget_to_dict(b: "PicBudgetState") -> dict:
+    d = {k: getattr(b, k) for k in BUDGET_KEYS}
+    d["E_esc"] = (b.E_esc[0], b.E_esc[1])
+    return d
+
+
+def budget_from_dict(d: dict) -> "PicBudgetState":
+    b = PicBudgetState()
+    b.valid = 1
+    b.nonfinite = int(d["nonfinite"])
+    for k in ("E_in", "E_out_left", "E_out_right", "E_rad", "n_stiff"):
+        setattr(b, k, float(d[k]))
+    b.E_esc[0], b.E_esc[1] = (float(x) for x in d["E_esc"])
+    return b
 
 
 class PicWave(C.Structure):
@@ -123,6 +157,7 @@ class PicState(C.Structure):
         ("Jy_int", C.c_void_p),
         ("Jz_int", C.c_void_p),
         ("step", C.c_int64),
+        ("budget", PicBudgetState),
     ]
 
 
@@ -210,6 +245,7 @@ class Pic2dState(C.Structure):
         ("Jz_int", C.c_void_p),
         ("charge_int", C.c_void_p),
         ("step", C.c_int64),
+        ("budget", PicBudgetState),
     ]
 
 
@@ -244,6 +280,8 @@ SIGNATURES = {
                                    C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]),
     "pic_batch_admit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
                                   C.POINTER(C.c_int32)]),
+    "pic_batch_fits": (C.c_int, [C.c_void_p, C.POINTER(PicConfig), C.POINTER(C.c_int32),
+                                 C.POINTER(C.c_int32)]),
     "pic_batch_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     "pic_batch_poll": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.c_void_p]),
     "pic_batch_release": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),

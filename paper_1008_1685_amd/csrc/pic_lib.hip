@@ -441,6 +441,14 @@ pic_status do_init(pic_run* r, hipStream_t st) {
   return PIC_OK;
 }
 
+// Total field energy and the residual of the energy balance (Section 2):
+// what is in the box, plus what was radiated or left it, minus what entered.
+void finish_balance(pic_diag_out* o) {
+  o->U_field = o->U_Ex + o->U_Et + o->U_B;
+  o->balance = o->U_field + o->K_e + o->K_i + o->E_rad + o->E_out_left + o->E_out_right + o->E_esc -
+               o->E_in;
+}
+
 template <typename R>
 pic_status do_diag(pic_run* r, pic_diag_out* out, hipStream_t st) {
   const Derived& d = r->d;
@@ -493,6 +501,7 @@ pic_status do_diag(pic_run* r, pic_diag_out* out, hipStream_t st) {
   out->gauss = (double)o.gauss_int * d.w_ref * std::ldexp(1.0, -32) / d.dx;
   out->n_stiff = (int64_t)o.n_stiff;
   out->nonfinite = flags[0] != 0;
+  finish_balance(out);
   if (step_dev != r->step)
     return fail(PIC_EHIP, "device step counter disagrees with the host (lost launch?)");
   if (out->nonfinite) return fail(PIC_ENONFINITE, "a particle momentum became non-finite");
@@ -593,6 +602,24 @@ pic_status write_ranges(pic_batch* b, hipStream_t st) {
   return update_batch_grids(b);
 }
 
+// Work-groups a run of n0 electrons, n1 ions and nx cells occupies in each
+// captured launch of a batch: push tiles, field chunks, sort tiles.
+void batch_need(long long n0, long long n1, int nx, int need[3]) {
+  need[0] = tiles_for(n0, kBatchTile) + tiles_for(n1, kBatchTile);
+  need[1] = (nx + 3 + kFieldChunk - 1) / kFieldChunk;
+  need[2] = sort_blocks_for(n0) + sort_blocks_for(n1);
+}
+
+// The resident runs leave room for `need`.
+bool batch_room(const pic_batch* b, const int need[3]) {
+  for (int k = 0; k < 3; ++k) {
+    long long used = 0;
+    for (int s = 0; s < b->max_slots; ++s) used += b->nblk[k][s];
+    if (used + need[k] > b->cap[k]) return false;
+  }
+  return true;
+}
+
 int batch_work(const pic_batch* b, int kind) {
   long long t = 0;
   for (int s = 0; s < b->max_slots; ++s) t += b->nblk[kind][s];
@@ -660,6 +687,39 @@ __global__ void k_gather_steps(const char* tab, size_t slot_bytes, size_t step_o
                                long long* out) {
   const int s = (int)(blockIdx.x * blockDim.x + threadIdx.x);
   if (s < n) out[s] = **reinterpret_cast<long long* const*>(tab + s * slot_bytes + step_off);
+}
+
+// ---------------------------------------------------------------- checkpointed budget
+// The per-tile accumulators hold, per push work-group slot, the radiated
+// energy, the escaped energy of each species and the stiff-push count.
+// A checkpoint carries their totals; a restore puts the totals in slot 0 and
+// clears the rest, so the run's sums continue from them.
+pic_status read_tile_budget(const double* acc, int tiles, const int* flags, pic_budget_state* b) {
+  std::vector<double> a(4 * (size_t)std::max(tiles, 1));
+  HIP_TRY(hipMemcpy(a.data(), acc, a.size() * sizeof(double), hipMemcpyDeviceToHost));
+  double t[4] = {0.0, 0.0, 0.0, 0.0};
+  for (size_t i = 0; i < a.size(); ++i) t[i % 4] += a[i];
+  b->E_rad = t[0];
+  b->E_esc[0] = t[1];
+  b->E_esc[1] = t[2];
+  b->n_stiff = t[3];
+  int f = 0;
+  HIP_TRY(hipMemcpy(&f, flags, sizeof(int), hipMemcpyDeviceToHost));
+  b->nonfinite = f != 0;
+  b->valid = 1;
+  return PIC_OK;
+}
+
+pic_status write_tile_budget(double* acc, int tiles, int* flags, const pic_budget_state* b) {
+  std::vector<double> a(4 * (size_t)std::max(tiles, 1), 0.0);
+  a[0] = b->E_rad;
+  a[1] = b->E_esc[0];
+  a[2] = b->E_esc[1];
+  a[3] = b->n_stiff;
+  HIP_TRY(hipMemcpy(acc, a.data(), a.size() * sizeof(double), hipMemcpyHostToDevice));
+  const int f = b->nonfinite ? 1 : 0;
+  HIP_TRY(hipMemcpy(flags, &f, sizeof(int), hipMemcpyHostToDevice));
+  return PIC_OK;
 }
 
 
@@ -875,6 +935,15 @@ pic_status pic_get_state(pic_run* r, pic_state* st, void* stream) {
     if (js[k])
       HIP_TRY(hipMemcpy(js[k], r->J[r->step & 1][k], jl[k] * sizeof(long long), hipMemcpyDeviceToHost));
   st->step = r->step;
+  {
+    double bud[4];
+    HIP_TRY(hipMemcpy(bud, r->budget, sizeof(bud), hipMemcpyDeviceToHost));
+    st->budget.E_in = bud[0];
+    st->budget.E_out_left = bud[1];
+    st->budget.E_out_right = bud[2];
+    pic_status ps = read_tile_budget(r->acc, r->tiles_max, r->flags, &st->budget);
+    if (ps) return ps;
+  }
   return PIC_OK;
 }
 
@@ -963,6 +1032,12 @@ pic_status pic_set_state(pic_run* r, const pic_state* st, void* stream) {
   for (int k = 0; k < 3; ++k)
     if (js[k])
       HIP_TRY(hipMemcpy(r->J[r->step & 1][k], js[k], jl[k] * sizeof(long long), hipMemcpyHostToDevice));
+  if (st->budget.valid) {
+    const double bud[4] = {st->budget.E_in, st->budget.E_out_left, st->budget.E_out_right, 0.0};
+    HIP_TRY(hipMemcpy(r->budget, bud, sizeof(bud), hipMemcpyHostToDevice));
+    pic_status ps = write_tile_budget(r->acc, r->tiles_max, r->flags, &st->budget);
+    if (ps) return ps;
+  }
   HIP_TRY(hipDeviceSynchronize());
   return PIC_OK;
 }
@@ -1141,13 +1216,11 @@ pic_status pic_batch_admit(pic_batch* b, pic_run* r, int64_t n_steps, void* stre
       break;
     }
   if (free_slot < 0) return fail(PIC_EBUSY, "no free batch slot");
-  const int need[3] = {tiles_for(r->n_max[0], kBatchTile) + tiles_for(r->n_max[1], kBatchTile), field_blocks_for(r),
-                       sort_blocks_for(r->n_max[0]) + sort_blocks_for(r->n_max[1])};
-  for (int k = 0; k < 3; ++k) {
-    long long used = 0;
-    for (int s = 0; s < b->max_slots; ++s) used += b->nblk[k][s];
-    if (used + need[k] > b->cap[k]) return fail(PIC_EBUSY, "batch work capacity exhausted");
-  }
+  int need[3];
+  batch_need(r->n_max[0], r->n_max[1], r->d.nx, need);
+  for (int k = 0; k < 3; ++k)
+    if (need[k] > b->cap[k]) return fail(PIC_EINVAL, "run exceeds the batch's work capacity");
+  if (!batch_room(b, need)) return fail(PIC_EBUSY, "batch work capacity exhausted");
   b->runs[free_slot] = r;
   b->target[free_slot] = n_steps;
   for (int k = 0; k < 3; ++k) b->nblk[k][free_slot] = need[k];
@@ -1163,6 +1236,24 @@ pic_status pic_batch_admit(pic_batch* b, pic_run* r, int64_t n_steps, void* stre
   }
   r->batch = b;
   *slot = free_slot;
+  return PIC_OK;
+}
+
+pic_status pic_batch_fits(const pic_batch* b, const pic_config* cfg, int32_t* now, int32_t* ever) {
+  if (!b || !cfg || !now || !ever) return fail(PIC_EINVAL, "null batch, config or output");
+  Derived d;
+  pic_status ps = derive(cfg, &d);
+  if (ps) return ps;
+  if (d.prec != b->prec) return fail(PIC_EINVAL, "run precision differs from the batch");
+  if (cfg->sort_interval != b->quantum) return fail(PIC_EINVAL, "run sort_interval must equal the batch quantum");
+  int need[3];
+  batch_need(d.n_foil, d.n_foil, d.nx, need);
+  *ever = 1;
+  for (int k = 0; k < 3; ++k)
+    if (need[k] > b->cap[k]) *ever = 0;
+  bool slot = false;
+  for (int s = 0; s < b->max_slots; ++s) slot = slot || !b->runs[s];
+  *now = (*ever && slot && batch_room(b, need)) ? 1 : 0;
   return PIC_OK;
 }
 

@@ -117,10 +117,11 @@ class Run:
             N.check(st, "pic_diag")
         d = {k: getattr(o, k) for k, _ in N.PicDiagOut._fields_ if k != "reserved"}
         d["n_alive"] = (o.n_alive[0], o.n_alive[1])
-        d["U_field"] = o.U_Ex + o.U_Et + o.U_B
-        d["balance"] = (d["U_field"] + o.K_e + o.K_i + o.E_rad + o.E_out_left + o.E_out_right
-                        + o.E_esc - o.E_in)
         return d
+
+    def has_residuals(self) -> bool:
+        return (self.rdt == np.float32 and bool(self.cfg["rr"])
+                and bool(self.cfg.get("rr_compensated", True)))
 
     def get_state(self, residuals: bool = True, particles: bool = True) -> dict:
         """Fields, currents and (unless particles=False) the alive particles."""
@@ -137,7 +138,8 @@ class Run:
                 continue
             arrs = dict(cell=np.empty(cap, np.int32), off=np.empty(cap, rdt), ux=np.empty(cap, rdt),
                         uy=np.empty(cap, rdt), uz=np.empty(cap, rdt), w=np.empty(cap, rdt))
-            if s == 0 and residuals:
+            # residuals exist for FP32 electrons under compensated RR only
+            if s == 0 and residuals and self.has_residuals():
                 for k in ("rx", "ry", "rz"):
                     arrs[k] = np.empty(cap, np.float32)
             sp = st.sp[s]
@@ -154,6 +156,7 @@ class Run:
         N.check(self.lib.pic_get_state(self._h, C.byref(st), self._stream()), "pic_get_state")
         res = dict(f)
         res["step"] = st.step
+        res["budget"] = N.budget_to_dict(st.budget)
         if particles:
             for s in range(2):
                 cnt = st.sp[s].count
@@ -167,7 +170,7 @@ class Run:
         rdt = self.rdt
         dt = dict(cell=np.int32, off=rdt, ux=rdt, uy=rdt, uz=rdt, w=rdt)
         arrs = {k: np.empty(count, dt[k]) for k in keys}
-        if residuals:
+        if residuals and species == 0 and self.has_residuals():
             for k in ("rx", "ry", "rz"):
                 arrs[k] = np.empty(count, np.float32)
         sp = N.PicSpeciesState()
@@ -178,9 +181,10 @@ class Run:
         return {k: a[: sp.count] for k, a in arrs.items()}
 
     def set_state(self, particles: dict | None = None, fields: dict | None = None,
-                  step: int = -1):
+                  step: int = -1, budget: dict | None = None):
         """particles: {0: {...}, 1: {...}} with cell, off, ux, uy, uz, w (+ rx, ry, rz);
-        fields: any of Ex, Ey, Ez, By, Bz, Ex_int."""
+        fields: any of Ex, Ey, Ez, By, Bz, Ex_int, Jx_int, Jy_int, Jz_int; budget: the
+        "budget" dict of get_state (cumulative budget terms and the non-finite flag)."""
         st = N.PicState()
         keep = []
         for s in range(2):
@@ -212,6 +216,8 @@ class Run:
             keep.append(a)
             setattr(st, k, _ptr(a))
         st.step = int(step)
+        if budget is not None:
+            st.budget = N.budget_from_dict(budget)
         N.check(self.lib.pic_set_state(self._h, C.byref(st), self._stream()), "pic_set_state")
 
     def spectrum(self, bins: int, e_max_mev: float) -> np.ndarray:

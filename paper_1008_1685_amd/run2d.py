@@ -108,9 +108,6 @@ class Run2D:
         N.check(self.lib.pic2d_diag(self._h, C.byref(o), self._stream()), "pic2d_diag")
         d = {k: getattr(o, k) for k, _ in N.PicDiagOut._fields_ if k != "reserved"}
         d["n_alive"] = (o.n_alive[0], o.n_alive[1])
-        d["U_field"] = o.U_Ex + o.U_Et + o.U_B
-        d["balance"] = (d["U_field"] + o.K_e + o.K_i + o.E_rad + o.E_out_left + o.E_out_right
-                        + o.E_esc - o.E_in)
         return d
 
     def _shapes(self):
@@ -155,6 +152,7 @@ class Run2D:
         N.check(self.lib.pic2d_get_state(self._h, C.byref(st), self._stream()), "pic2d_get_state")
         res = dict(grids)
         res["step"] = st.step
+        res["budget"] = N.budget_to_dict(st.budget)
         if particles:
             for s in range(2):
                 cnt = st.sp[s].count
@@ -162,9 +160,10 @@ class Run2D:
         return res
 
     def set_state(self, particles: dict | None = None, fields: dict | None = None,
-                  step: int = -1):
+                  step: int = -1, budget: dict | None = None):
         """particles: {0: {...}, 1: {...}} with cell, ox, oy, ux, uy, uz, w (+ rx, ry, rz);
-        fields: any of Ex, Ey, Ez, Bx, By, Bz, Jx_int, Jy_int, Jz_int, charge_int."""
+        fields: any of Ex, Ey, Ez, Bx, By, Bz, Jx_int, Jy_int, Jz_int, charge_int;
+        budget: the "budget" dict of get_state."""
         st = N.Pic2dState()
         keep = []
         for s in range(2):
@@ -193,6 +192,8 @@ class Run2D:
             keep.append(a)
             setattr(st, k, _ptr(a))
         st.step = int(step)
+        if budget is not None:
+            st.budget = N.budget_from_dict(budget)
         N.check(self.lib.pic2d_set_state(self._h, C.byref(st), self._stream()), "pic2d_set_state")
         self.info = self.get_info()
 

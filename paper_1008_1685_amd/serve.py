@@ -48,14 +48,16 @@ class Batch:
                 "pic_batch_admit")
         return slot.value
 
-    def try_admit(self, run: Run, n_steps: int):
-        """Slot index, or None when no slot or work capacity is free."""
-        slot = C.c_int32(-1)
-        st = self.lib.pic_batch_admit(self._h, run._h, int(n_steps), self._st(), C.byref(slot))
-        if st == N.PIC_EBUSY:
-            return None
-        N.check(st, "pic_batch_admit")
-        return slot.value
+    def fits(self, cfg: dict):
+        """(now, ever): whether a run of ``cfg`` would be admitted at this
+        moment, and whether it fits an empty batch at all."""
+        from .run import make_config
+
+        c = make_config(cfg)
+        now, ever = C.c_int32(0), C.c_int32(0)
+        N.check(self.lib.pic_batch_fits(self._h, C.byref(c), C.byref(now), C.byref(ever)),
+                "pic_batch_fits")
+        return bool(now.value), bool(ever.value)
 
     def step(self, n_quanta: int = 1):
         N.check(self.lib.pic_batch_step(self._h, int(n_quanta), self._st()), "pic_batch_step")
@@ -119,13 +121,17 @@ class Server:
                 req = queue[0]
                 need = workspace_bytes(req["cfg"])
                 if used + need > self.budget and active:
+                    break  # (a request larger than the whole budget runs alone)
+                fits_now, fits_ever = b.fits(req["cfg"])
+                if not fits_ever:
+                    raise ValueError(f"request {req['cfg'].get('name', '')!r} exceeds the batch's "
+                                     "work capacity (max_particles / max_cells)")
+                if not fits_now:
                     break
+                # the request is admitted: only now is its memory set aside
                 run = Run(req["cfg"], stream=b.stream)
                 steps = run_steps(req["cfg"])
-                slot = b.try_admit(run, steps)
-                if slot is None:
-                    run.close()
-                    break
+                slot = b.admit(run, steps)
                 queue.popleft()
                 used += need
                 self.peak_bytes = max(self.peak_bytes, used)

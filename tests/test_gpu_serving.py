@@ -1,5 +1,6 @@
 """Serving form on the GPU: continuous batching gives each run the result it
-gets alone, admits by device-memory budget and reuses slots."""
+gets alone and the oracle's result, admits by device-memory budget, reuses
+slots, and confines a failing run's error to that run."""
 import numpy as np
 import pytest
 
@@ -108,3 +109,77 @@ def test_every_run_of_a_request_stream_conserves_charge():
     bad = [(r["name"], r["diag"]["gauss_int"], r["diag"]["nonfinite"]) for r in recs
            if r["diag"]["gauss_int"] != 0 or r["diag"]["nonfinite"]]
     assert not bad, bad
+
+
+def test_served_runs_match_the_oracle():
+    # every served request against the FP64 oracle on its own configuration,
+    # at the tolerances of the short runs: each energy term within 2e-3 of the
+    # injected energy plus twice the oracle's own seed-to-seed spread (LP heats
+    # the electrons chaotically), the balance within 1e-3, alive counts exact
+    from oracle import pic as opic
+    from paper_1008_1685_amd.serve import Server, run_steps
+
+    keys = ("U_field", "K_e", "K_i", "E_rad", "E_out_left", "E_out_right", "E_esc")
+    cfgs = _req_cfgs()
+    reqs = [dict(arrival=0.002 * i, cfg=c) for i, c in enumerate(cfgs)]
+    srv = Server(budget_bytes=1 << 34, max_slots=4, max_particles=2 * 10 ** 6, max_cells=10 ** 5)
+    recs = {r["name"]: r for r in srv.serve(reqs)}
+    for c in cfgs:
+        d = recs[c["name"]]["diag"]
+        n = run_steps(c)
+        rows = [opic.Pic1D(dict(c, seed=c["seed"] + 100 * k)).run(n).diag() for k in range(3)]
+        ref = rows[0]
+        e_in = ref["E_in"]
+        assert d["E_in"] == pytest.approx(e_in, rel=1e-6)
+        assert d["gauss_int"] == 0
+        for k in keys:
+            vals = np.array([r[k] for r in rows])
+            tol = (2e-3 + 2 * np.ptp(vals) / e_in) * e_in
+            print(f"[{c['name']}] {k}: served {d[k] / e_in:.5f} oracle {vals.mean() / e_in:.5f} "
+                  f"tol {tol / e_in:.5f} (fraction of E_in)", flush=True)
+            assert abs(d[k] - vals.mean()) <= tol, (c["name"], k, d[k], vals)
+        assert abs(d["balance"] - ref["balance"]) <= 1e-3 * e_in
+
+
+def test_a_non_finite_request_flags_only_itself():
+    # a request whose state holds a NaN momentum shares the batch with three
+    # others: only it reports PIC_ENONFINITE (the particle dropped), and every
+    # other run ends bit for bit as it does alone
+    from paper_1008_1685_amd import PicError, Run
+    from paper_1008_1685_amd.serve import Batch, run_steps
+
+    cfgs = _req_cfgs()
+    alone = [_alone(c) for c in cfgs]
+    bad = dict(cfgs[1], name="nan", seed=7)
+    batch = Batch(max_slots=4, quantum=16, max_particles=2 * 10 ** 6, max_cells=10 ** 5)
+    entries = []
+    for c in (cfgs[0], bad, cfgs[1], cfgs[2]):
+        run = Run(c, stream=batch.stream)
+        if c is bad:
+            st = run.get_state()
+            n0 = st["sp0"]["cell"].size
+            st["sp0"]["ux"][n0 // 2] = np.nan
+            run.set_state({0: st["sp0"], 1: st["sp1"]}, step=0)
+        entries.append((c, run, batch.admit(run, run_steps(c))))
+    while True:
+        batch.step(2)
+        now = batch.poll()
+        if all(now[slot] >= run_steps(c) for c, _, slot in entries):
+            break
+    for c, run, slot in entries:
+        batch.release(slot)
+    for c, run, slot in entries:
+        if c is bad:
+            with pytest.raises(PicError, match="PIC_ENONFINITE"):
+                run.diag()
+            d = run.diag(allow_nonfinite=True)
+            # (the dropped particle's charge leaves without a current, so this
+            # run's Gauss law no longer closes: its result is flagged invalid)
+            assert d["nonfinite"] == 1 and d["n_alive"][1] == n0
+            assert d["n_alive"][0] <= n0 - 1
+            continue
+        k = [x["name"] for x in cfgs].index(c["name"])
+        d = run.diag()
+        assert d["nonfinite"] == 0
+        _same(*alone[k], run.get_state(), d)
+    batch.close()

@@ -42,3 +42,33 @@ def test_ion_energy_units():
     # a proton with gamma = 2 carries m_p c^2 = 1836 * 0.511 MeV of kinetic energy
     u = np.array([[np.sqrt(3.0), 0, 0]])
     assert spectrum.ion_energies_mev(u, 1836.0)[0] == pytest.approx(1836 * 0.51099895)
+
+
+def test_central_range_of_uniform_bins_is_exact():
+    # 10 bins of 2 MeV; content only in bins 2..6 (E in [4, 14)), evenly:
+    # 10% of it lies below 5 MeV, 90% below 13 MeV
+    edges = np.linspace(0.0, 20.0, 11)
+    h = np.zeros(10)
+    h[2:7] = 3.0
+    lo, hi = spectrum.central_range(h, edges)
+    assert lo == pytest.approx(5.0, abs=1e-12) and hi == pytest.approx(13.0, abs=1e-12)
+    assert spectrum.width80(h, edges) == pytest.approx(8.0, abs=1e-12)
+    # an asymmetric case: content 1, 3 in bins [0, 2), [2, 4): the 10th
+    # percentile is 0.4 of the way through bin 0, the 90th 0.8666.. through bin 1
+    lo, hi = spectrum.central_range(np.array([1.0, 3.0]), np.array([0.0, 2.0, 4.0]))
+    assert lo == pytest.approx(0.8) and hi == pytest.approx(2.0 + 2.0 * (3.6 - 1.0) / 3.0)
+
+
+def test_central_range_of_a_gaussian():
+    r = np.random.default_rng(1)
+    mu, sig = 300.0, 12.0
+    E = r.normal(mu, sig, size=2_000_000)
+    h, edges = spectrum.histogram(E, np.ones_like(E), 2048, 600.0)
+    lo, hi = spectrum.central_range(h, edges)
+    z90 = 1.2815515655446004  # standard normal 90th percentile
+    assert lo == pytest.approx(mu - z90 * sig, abs=0.05)
+    assert hi == pytest.approx(mu + z90 * sig, abs=0.05)
+    # weights count, not particles: doubling half the sample's weights moves the range
+    w = np.where(E > mu, 2.0, 1.0)
+    h2, _ = spectrum.histogram(E, w, 2048, 600.0)
+    assert spectrum.central_range(h2, edges)[0] > lo + 1.0

@@ -9,7 +9,10 @@ from workloads import poisson_stream, preset
 
 
 class FakeRun:
+    made = 0
+
     def __init__(self, cfg, stream=None, **kw):
+        FakeRun.made += 1
         self.cfg = cfg
         self.info = dict(n_init=(10, 10))
         self._h = object()
@@ -29,14 +32,19 @@ class FakeBatch:
         self.stream = None
         self.admitted = []
 
-    def try_admit(self, run, n_steps):
+    def fits(self, cfg):
+        # work capacity of the stand-in: runs of more than 1e4 particles never fit
+        ever = cfg.get("ppc", 0) <= 10 ** 4
+        return ever and any(s is None for s in self.slots), ever
+
+    def admit(self, run, n_steps):
         for i, s in enumerate(self.slots):
             if s is None:
                 run.step, run.target = 0, n_steps
                 self.slots[i] = run
                 self.admitted.append(run.cfg["name"])
                 return i
-        return None
+        raise AssertionError("admit called without a free slot")
 
     def step(self, n):
         for r in self.slots:
@@ -93,6 +101,23 @@ def test_a_run_larger_than_the_budget_runs_alone(fakes):
     recs = srv.serve(_reqs(3))
     assert len(recs) == 3
     assert srv.peak_bytes == 5000  # admitted only into an empty batch
+
+
+def test_runs_are_built_only_when_admission_succeeds(fakes):
+    # two slots, five requests: every Run built is admitted at once (none is
+    # built, then freed again, while the batch is full)
+    FakeRun.made = 0
+    srv = S.Server(budget_bytes=10 ** 9, max_slots=2)
+    recs = srv.serve(_reqs(5))
+    assert len(recs) == 5 and FakeRun.made == 5
+
+
+def test_a_request_that_can_never_fit_raises(fakes):
+    reqs = _reqs(2)
+    reqs[1]["cfg"]["ppc"] = 10 ** 5
+    srv = S.Server(budget_bytes=10 ** 9, max_slots=2)
+    with pytest.raises(ValueError, match="work capacity"):
+        srv.serve(reqs)
 
 
 def test_poisson_stream_shape():

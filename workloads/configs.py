@@ -44,6 +44,10 @@ _BASE = dict(
 PRESETS = {
     # small plain run that the FP64 oracle finishes
     "c1": dict(_BASE),
+    # the small run at 512 particles per cell per species (102,400 particles):
+    # enough protons to resolve the spectrum's peak and width in whole-run
+    # comparisons (the oracle finishes it in minutes)
+    "c1w": dict(_BASE, ppc=512),
     # plain method at scale: LP a0=300, 12,000 cells, 4e5 particles
     "c2": dict(_BASE, cells_per_lambda=200, box_lambda=60.0, pol="LP", a0=300.0,
                n0=100.0, ppc=1000, periods=60.0, precision="fp64"),
