@@ -148,6 +148,12 @@ struct pic_run {
   int tiles_max;
   int push_tile = kTile;  // particles per push work-group: kTile, or kBatchTile for small runs
   struct pic_batch* batch = nullptr;  // set while the run is stepped by a batch
+  // pic_step replays two sort intervals at a time as one captured graph (the
+  // kernel arguments repeat with that period: step parity and sort parity
+  // both return); one graph per (sort parity, step parity) at its start
+  hipGraphExec_t step_graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  hipGraph_t step_graph_def[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  hipStream_t capture_stream = nullptr;  // a stream to record on; replays go to the caller's
   // timing: every timing-th launch of each kernel kind is bracketed by events
   int timing = 0;
   long long seen[3] = {0, 0, 0};
@@ -361,10 +367,20 @@ SortArgs<R> make_sort_args(const pic_run* r, int pp) {
   return p;
 }
 
+// Launches of one step's kernels.  `capture`: the launch is being recorded
+// into a graph (plain launches, no timing events).
 template <typename R>
-pic_status launch_push(pic_run* r, hipStream_t st) {
+pic_status launch_push(pic_run* r, hipStream_t st, bool capture = false) {
   const PushArgs<R> a = make_push_args<R>(r, r->pp, (int)(r->step & 1), r->push_tile);
   if (a.ntiles == 0) return PIC_OK;
+  if (capture) {
+    if (r->push_tile == kBatchTile)
+      hipLaunchKernelGGL(k_push_small<R>, dim3(a.ntiles), dim3(kThreads), 0, st, a);
+    else
+      hipLaunchKernelGGL(k_push<R>, dim3(a.ntiles), dim3(kThreads), 0, st, a);
+    HIP_TRY(hipGetLastError());
+    return PIC_OK;
+  }
   size_t slot;
   hipEvent_t e0, e1;
   pic_status ps = ev_pick(r, 0, &slot, &e0, &e1);
@@ -379,49 +395,125 @@ pic_status launch_push(pic_run* r, hipStream_t st) {
 }
 
 template <typename R>
-pic_status launch_field(pic_run* r, hipStream_t st) {
+pic_status launch_field(pic_run* r, hipStream_t st, bool capture = false) {
   const FieldArgs<R> f = make_field_args<R>(r, (int)(r->step & 1), 1);
-  size_t slot;
-  hipEvent_t e0, e1;
-  pic_status ps = ev_pick(r, 1, &slot, &e0, &e1);
-  if (ps) return ps;
-  hipExtLaunchKernelGGL(k_field<R>, dim3(field_blocks_for(r)), dim3(kFieldChunk), 0, st, e0, e1, 0, f);
+  if (capture) {
+    hipLaunchKernelGGL(k_field<R>, dim3(field_blocks_for(r)), dim3(kFieldChunk), 0, st, f);
+  } else {
+    size_t slot;
+    hipEvent_t e0, e1;
+    pic_status ps = ev_pick(r, 1, &slot, &e0, &e1);
+    if (ps) return ps;
+    hipExtLaunchKernelGGL(k_field<R>, dim3(field_blocks_for(r)), dim3(kFieldChunk), 0, st, e0, e1, 0, f);
+    ev_done(r, slot);
+  }
   HIP_TRY(hipGetLastError());
-  ev_done(r, slot);
   r->step += 1;
   return PIC_OK;
 }
 
 template <typename R>
-pic_status launch_sort(pic_run* r, hipStream_t st) {
+pic_status launch_sort(pic_run* r, hipStream_t st, bool capture = false) {
   const SortArgs<R> p = make_sort_args<R>(r, r->pp);
   const int grid = p.blocks0 + sort_blocks_for(r->n_max[1]);
-  size_t slot;
-  hipEvent_t e0, e1;
-  pic_status ps = ev_pick(r, 2, &slot, &e0, &e1);
-  if (ps) return ps;
+  size_t slot = kNoEvent;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (!capture) {
+    pic_status ps = ev_pick(r, 2, &slot, &e0, &e1);
+    if (ps) return ps;
+  }
   // the events span the three passes: start of the histogram, end of the scatter
-  hipExtLaunchKernelGGL(k_sort_hist<R>, dim3(grid), dim3(kSortThreads), 0, st, e0, nullptr, 0, p);
+  if (capture)
+    hipLaunchKernelGGL(k_sort_hist<R>, dim3(grid), dim3(kSortThreads), 0, st, p);
+  else
+    hipExtLaunchKernelGGL(k_sort_hist<R>, dim3(grid), dim3(kSortThreads), 0, st, e0, nullptr, 0, p);
   hipLaunchKernelGGL(k_sort_scan, dim3(2), dim3(1024), 0, st, r->cnt[0], r->cnt[1], r->cursor[0],
                      r->cursor[1], r->count + 2 * (r->pp ^ 1), r->d.nx);
-  hipExtLaunchKernelGGL(k_sort_scatter<R>, dim3(grid), dim3(kSortThreads), 0, st, nullptr, e1, 0, p);
+  if (capture)
+    hipLaunchKernelGGL(k_sort_scatter<R>, dim3(grid), dim3(kSortThreads), 0, st, p);
+  else
+    hipExtLaunchKernelGGL(k_sort_scatter<R>, dim3(grid), dim3(kSortThreads), 0, st, nullptr, e1, 0, p);
   HIP_TRY(hipGetLastError());
-  ev_done(r, slot);
+  if (!capture) ev_done(r, slot);
   r->pp ^= 1;
   return PIC_OK;
 }
 
 template <typename R>
-pic_status do_steps(pic_run* r, int64_t n, hipStream_t st) {
-  for (int64_t k = 0; k < n; ++k) {
-    if (r->step > 0 && r->step % r->cfg.sort_interval == 0) {
-      pic_status ps = launch_sort<R>(r, st);
-      if (ps) return ps;
+pic_status one_step(pic_run* r, hipStream_t st, bool capture = false) {
+  if (r->step > 0 && r->step % r->cfg.sort_interval == 0) {
+    pic_status ps = launch_sort<R>(r, st, capture);
+    if (ps) return ps;
+  }
+  pic_status ps = launch_push<R>(r, st, capture);
+  if (ps) return ps;
+  return launch_field<R>(r, st, capture);
+}
+
+// Longest stretch (two sort intervals) replayed as one graph; runs that sort
+// more rarely step launch by launch.
+constexpr int64_t kMaxGraphSteps = 1024;
+
+void drop_step_graphs(pic_run* r) {
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      if (r->step_graph[a][b]) (void)hipGraphExecDestroy(r->step_graph[a][b]);
+      if (r->step_graph_def[a][b]) (void)hipGraphDestroy(r->step_graph_def[a][b]);
+      r->step_graph[a][b] = nullptr;
+      r->step_graph_def[a][b] = nullptr;
     }
-    pic_status ps = launch_push<R>(r, st);
+}
+
+// Record the 2 sort_interval steps from the current (sort) step into a graph
+// for (pp, step parity); the host's step and sort parity advance as the
+// recording does, exactly as the replay will on the device.
+template <typename R>
+pic_status capture_steps(pic_run* r, int64_t span) {
+  if (!r->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&r->capture_stream, hipStreamNonBlocking));
+  const int pp = r->pp, fp = (int)(r->step & 1);
+  HIP_TRY(hipStreamBeginCapture(r->capture_stream, hipStreamCaptureModeThreadLocal));
+  pic_status ps = PIC_OK;
+  for (int64_t k = 0; k < span && !ps; ++k) ps = one_step<R>(r, r->capture_stream, true);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(r->capture_stream, &g);
+  if (ps) {
+    if (g) (void)hipGraphDestroy(g);
+    return ps;
+  }
+  if (e != hipSuccess) return fail(PIC_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  hipGraphExec_t x = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (ei != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return fail(PIC_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+  }
+  r->step_graph_def[pp][fp] = g;
+  r->step_graph[pp][fp] = x;
+  r->step -= span;  // the recording advanced the host state; the launch does it again
+  r->pp = pp;
+  return PIC_OK;
+}
+
+template <typename R>
+pic_status do_steps(pic_run* r, int64_t n, hipStream_t st) {
+  const int64_t span = 2 * (int64_t)r->cfg.sort_interval;
+  while (n > 0) {
+    const bool at_sort = r->step > 0 && r->step % r->cfg.sort_interval == 0;
+    if (at_sort && !r->timing && span <= kMaxGraphSteps && n >= span) {
+      const int pp = r->pp, fp = (int)(r->step & 1);
+      if (!r->step_graph[pp][fp]) {
+        pic_status ps = capture_steps<R>(r, span);
+        if (ps) return ps;
+      }
+      for (; n >= span; n -= span) {
+        HIP_TRY(hipGraphLaunch(r->step_graph[pp][fp], st));
+        r->step += span;  // two sorts: the sort parity is back where it was
+      }
+      continue;
+    }
+    pic_status ps = one_step<R>(r, st);
     if (ps) return ps;
-    ps = launch_field<R>(r, st);
-    if (ps) return ps;
+    --n;
   }
   return PIC_OK;
 }
@@ -840,6 +932,8 @@ void pic_free(pic_run* r) {
     (void)hipEventDestroy(e.a);
     (void)hipEventDestroy(e.b);
   }
+  drop_step_graphs(r);
+  if (r->capture_stream) (void)hipStreamDestroy(r->capture_stream);
   delete r;
 }
 
@@ -955,6 +1049,7 @@ pic_status pic_set_state(pic_run* r, const pic_state* st, void* stream) {
   const size_t rs = rsz(r);
   HIP_TRY(hipStreamSynchronize(s));
   HIP_TRY(hipMemset(r->tpred, 0, 2 * sizeof(int)));  // the tile ranges no longer hold
+  drop_step_graphs(r);  // particle counts (launch grids) may change
   if (st->step >= 0 && st->step != r->step) {
     // move the fields to the buffer parity of the new step
     const int po = (int)(r->step & 1), pn = (int)(st->step & 1);

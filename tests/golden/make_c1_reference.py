@@ -2,8 +2,8 @@
 whole-run values of the oracle for the small laser-foil workload (CP
 a0 = 200, n0 = 90, 1 wavelength foil at 8 wavelengths, 100 cells per
 wavelength, sin^2 pulse of 10 periods, RR on, 30 periods = 6,000 steps) at
-64 particles per cell per species ("c1", 12,800 particles; seeds 0-7) and at
-512 ("c1w", 102,400 particles; seeds 0-2).
+64 particles per cell per species ("c1", 12,800 particles) and at 512 ("c1w",
+102,400 particles), seeds 0-7 each.
 
 Stored per run:
 * the energy budget (Section 2 energy balance) every 500 steps as fractions
@@ -43,7 +43,7 @@ KEYS = ("U_Ex", "U_Et", "U_B", "U_field", "K_e", "K_i", "E_rad", "E_out_left",
         "E_out_right", "E_esc", "balance")
 EVERY = 500
 CASES = ([("c1", s, False) for s in range(8)] + [("c1", s, True) for s in range(3)]
-         + [("c1w", s, False) for s in range(3)] + [("c1w", 0, True)])
+         + [("c1w", s, False) for s in range(8)] + [("c1w", 0, True)])
 
 
 def out_path(workload: str, seed: int, f32_start: bool) -> str:
