@@ -258,6 +258,18 @@ pic_status pic_set_state(struct pic_run* run, const pic_state* st, void* stream)
 pic_status pic_spectrum(struct pic_run* run, int32_t bins, double e_max_mev,
                         double* host_hist, void* stream);
 
+/* pic_spectrum for callers that cannot allocate device memory: the same
+ * histogram, with its counters in a fixed device array inside the library
+ * (512 KiB per device, held until the process ends) instead of the run's
+ * workspace.  At most 65536 bins (more: PIC_EINVAL).  host_hist (bins
+ * doubles) also serves as the staging buffer of the counts, so the call
+ * allocates nothing.  Every call on one device shares that array: calls
+ * that overlap on one device (several threads, or streams running at once)
+ * race and must be serialised by the caller; each call clears the bins it
+ * uses.  Blocking. */
+pic_status pic_spectrum_static(struct pic_run* run, int32_t bins, double e_max_mev,
+                               double* host_hist, void* stream);
+
 /* ------------------------------------------------------------------------
  * Test electrons in a given plane wave (the single-particle tests of
  * Section 3): independent of any run.  The wave travels along +x with

@@ -12,10 +12,19 @@
 #include <cstdio>
 #include <cstddef>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
 using namespace pic;
+
+// Histogram counters of pic_spectrum_static: a fixed device array, so that
+// entry point needs no device memory from the caller or the allocator.  Each
+// device that calls it holds its own copy until the process ends.  In host
+// code this name is not a device address: host code uses the per-device
+// address from hipGetSymbolAddress (static_scratch below).
+constexpr int kStaticSpectrumBins = 1 << 16;  // 512 KiB of 64-bit counters
+static __device__ __align__(256) unsigned long long scratch[kStaticSpectrumBins];
 
 namespace {
 
@@ -781,6 +790,33 @@ __global__ void k_gather_steps(const char* tab, size_t slot_bytes, size_t step_o
   if (s < n) out[s] = **reinterpret_cast<long long* const*>(tab + s * slot_bytes + step_off);
 }
 
+// ---------------------------------------------------------------- static scratch
+__global__ void k_fill_u64(unsigned long long* p, int n, unsigned long long v) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i < n) p[i] = v;
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned long long* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of this device's copy of `scratch`, looked up once per device with
+// that device current (every device has its own copy at its own address).
+pic_status static_scratch(unsigned long long** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(PIC_EINVAL, "device index beyond the static scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(PIC_EHIP, "hipGetSymbolAddress returned a null address");
+    g_scratch_ptr[dev] = static_cast<unsigned long long*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return PIC_OK;
+}
+
 // ---------------------------------------------------------------- checkpointed budget
 // The per-tile accumulators hold, per push work-group slot, the radiated
 // energy, the escaped energy of each species and the stiff-push count.
@@ -1134,6 +1170,38 @@ pic_status pic_set_state(pic_run* r, const pic_state* st, void* stream) {
     if (ps) return ps;
   }
   HIP_TRY(hipDeviceSynchronize());
+  return PIC_OK;
+}
+
+pic_status pic_spectrum_static(pic_run* r, int32_t bins, double e_max, double* host_hist, void* stream) {
+  if (!r || !host_hist || bins < 1 || !(e_max > 0)) return fail(PIC_EINVAL, "bad spectrum arguments");
+  if (bins > kStaticSpectrumBins)
+    return fail(PIC_EINVAL, "pic_spectrum_static takes at most " + std::to_string(kStaticSpectrumBins) + " bins");
+  if (r->batch) return fail(PIC_EBUSY, "run is stepped by a batch; release it first");
+  unsigned long long* hist = nullptr;
+  pic_status ps = static_scratch(&hist);
+  if (ps) return ps;
+  hipStream_t s = S(stream);
+  // the array keeps the last call's counts: clear the bins this call uses
+  hipLaunchKernelGGL(k_fill_u64, dim3((bins + 255) / 256), dim3(256), 0, s, hist, bins, 0ull);
+  const double mc2 = r->cfg.mass_ratio * kMec2_MeV;
+  if (r->d.prec == PIC_FP32)
+    hipLaunchKernelGGL(k_spectrum<float>, dim3(1024), dim3(256), 0, s, dev<float>(r->sp[1][r->pp]),
+                       r->count + 2 * r->pp + 1, hist, bins, e_max, mc2, (float)(256.0 / r->d.w_ref));
+  else
+    hipLaunchKernelGGL(k_spectrum<double>, dim3(1024), dim3(256), 0, s, dev<double>(r->sp[1][r->pp]),
+                       r->count + 2 * r->pp + 1, hist, bins, e_max, mc2, 256.0 / r->d.w_ref);
+  HIP_TRY(hipGetLastError());
+  // the 64-bit counts land in the caller's array and are converted in place
+  static_assert(sizeof(double) == sizeof(unsigned long long), "in-place conversion");
+  HIP_TRY(hipMemcpyAsync(host_hist, hist, bins * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const double de = e_max / bins, unit = r->d.w_ref / 256.0;
+  for (int b = 0; b < bins; ++b) {
+    long long c;
+    std::memcpy(&c, host_hist + b, sizeof(c));
+    host_hist[b] = (double)c * unit / de;
+  }
   return PIC_OK;
 }
 

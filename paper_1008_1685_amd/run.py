@@ -227,6 +227,15 @@ class Run:
                 "pic_spectrum")
         return h
 
+    def spectrum_static(self, bins: int, e_max_mev: float) -> np.ndarray:
+        """As spectrum(), through the entry point that keeps its counters in
+        the library's fixed device array (no device memory of its own)."""
+        h = np.zeros(bins, np.float64)
+        N.check(self.lib.pic_spectrum_static(self._h, int(bins), float(e_max_mev),
+                                             h.ctypes.data_as(C.POINTER(C.c_double)), self._stream()),
+                "pic_spectrum_static")
+        return h
+
     # ------------------------------------------------------------ timing
     def timing(self, period):
         """Time every ``period``-th launch of each kernel kind (True: every
