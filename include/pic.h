@@ -270,6 +270,18 @@ pic_status pic_spectrum(struct pic_run* run, int32_t bins, double e_max_mev,
 pic_status pic_spectrum_static(struct pic_run* run, int32_t bins, double e_max_mev,
                                double* host_hist, void* stream);
 
+/* Friction coefficient of Eq. (damping), the strength of the RR force in
+ * units of m omega c (Section 2): d = eps gamma^2 [f_L^2 - (v.f_L)^2] with
+ * f_L = -(E + v x B), for every electron at the current step (E^n, B^n
+ * gathered at x^n as the push gathers them, v from the stored momentum),
+ * in FP64.  host_hist[bins]: electron weight (density x length) with
+ * log10 d in bin floor((log10 d - log10_lo) / (log10_hi - log10_lo) bins);
+ * host_stats[4]: the maximum of d, the weight-averaged d, the weight with
+ * d <= 0 or log10 d < log10_lo, and the weight with log10 d >= log10_hi.
+ * bins <= 65531.  Blocking. */
+pic_status pic_friction(struct pic_run* run, int32_t bins, double log10_lo, double log10_hi,
+                        double* host_hist, double* host_stats, void* stream);
+
 /* ------------------------------------------------------------------------
  * Test electrons in a given plane wave (the single-particle tests of
  * Section 3): independent of any run.  The wave travels along +x with

@@ -143,6 +143,33 @@ class PlaneWaveOrbit:
         return x, u, phi
 
 
+def px_time_lag(orbit, t, px, span=1.0, step=1e-4):
+    """Phase error of a computed longitudinal momentum against the exact
+    orbit (Section 3 quotes it for its worked example): the time shift tau,
+    |tau| <= span, that best maps the samples px(t) onto the exact p_x, in the
+    least-squares sense (the exact p_x(t + tau) from the orbit's dense
+    solution, sampled on a fine grid of phases and interpolated linearly)."""
+    t = np.asarray(t, dtype=np.float64)
+    px = np.asarray(px, dtype=np.float64)
+    _, _, ph_lo = orbit.at_time(t.min() - span - 0.1)
+    _, _, ph_hi = orbit.at_time(t.max() + span + 0.1)
+    ph = np.linspace(ph_lo, ph_hi, 200001)
+    tt = np.empty_like(ph)
+    ux = np.empty_like(ph)
+    for i, p in enumerate(ph):
+        tt[i], _, u = orbit.at_phase(p)
+        ux[i] = u[0]
+    taus = np.arange(-span, span + 0.5 * step, step)
+    err = np.array([np.sum((np.interp(t + tau, tt, ux) - px) ** 2) for tau in taus])
+    k = int(np.argmin(err))
+    if 0 < k < taus.size - 1:  # parabola through the three smallest
+        y0, y1, y2 = err[k - 1], err[k], err[k + 1]
+        den = y0 - 2.0 * y1 + y2
+        if den > 0:
+            return float(taus[k] + 0.5 * step * (y0 - y2) / den)
+    return float(taus[k])
+
+
 def boris_rotation_angle(qm, B_abs, dt, gamma):
     """Angle of one Boris rotation in a pure magnetic field."""
     return 2.0 * np.arctan(abs(qm) * B_abs * dt / (2.0 * gamma))

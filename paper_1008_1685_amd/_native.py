@@ -274,6 +274,8 @@ SIGNATURES = {
                                C.c_void_p]),
     "pic_spectrum_static": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.POINTER(C.c_double),
                                       C.c_void_p]),
+    "pic_friction": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.POINTER(C.c_double),
+                               C.POINTER(C.c_double), C.c_void_p]),
     "pic_timing_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "pic_timing_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                   C.c_void_p]),

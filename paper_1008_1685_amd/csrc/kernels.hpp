@@ -1868,4 +1868,73 @@ __global__ void k_spectrum(SpeciesDev<R> sp, const long long* count, unsigned lo
   }
 }
 
+// ---------------------------------------------------------------- friction coefficient
+// The friction coefficient d of Eq. (damping) of every electron at the
+// current step: d = eps gamma^2 [f_L^2 - (v.f_L)^2], f_L = -(E + v x B), with
+// E^n, B^n gathered at x^n by the push's linear weights and v from the stored
+// momentum; FP64 throughout.  Each electron adds its weight (FP64) to bin
+// floor((log10 d - lo) / (hi - lo) bins), or to the under (d <= 0 or below
+// lo) or over slot; a block's maximum of d and sums of w d and w go out with
+// one atomic each.  out[bins + 0]: under, [+1]: over, [+2]: max d (bits: d >= 0
+// orders as an integer), [+3]: sum of w d, [+4]: sum of w.
+template <typename R>
+__global__ __launch_bounds__(256) void k_friction(SpeciesDev<R> sp, FieldsDev<R> f,
+                                                  const long long* count, double* out, int bins,
+                                                  double lo, double hi, double eps) {
+  __shared__ double s_max[256], s_sum[256], s_w[256];
+  const long long n = *count;
+  double dmax = 0.0, wd = 0.0, ws = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int c = sp.cell[i];
+    if (c == kDead) continue;
+    const double o = sp.off[i], on = 1.0 - o;
+    const NodeF<R> n0 = f.N[c], n1 = f.N[c + 1];
+    const double ey = on * (double)n0.ey + o * (double)n1.ey;
+    const double ez = on * (double)n0.ez + o * (double)n1.ez;
+    const double sx = o + 0.5;
+    const int hb = sx >= 1.0;
+    const double fh = hb ? sx - 1.0 : sx, fn = 1.0 - fh;
+    const HalfF<R> h0 = f.H[c + hb], h1 = f.H[c + hb + 1];
+    const double ex = fn * (double)h0.ex + fh * (double)h1.ex;
+    const double by = fn * (double)h0.by + fh * (double)h1.by;
+    const double bz = fn * (double)h0.bz + fh * (double)h1.bz;
+    const double ux = sp.ux[i], uy = sp.uy[i], uz = sp.uz[i];
+    const double g2 = 1.0 + ux * ux + uy * uy + uz * uz, g = sqrt(g2);
+    const double vx = ux / g, vy = uy / g, vz = uz / g;
+    // f_L = -(E + v x B), B = (0, by, bz)
+    const double fx = -(ex + (vy * bz - vz * by));
+    const double fy = -(ey - vx * bz);
+    const double fz = -(ez + vx * by);
+    const double vf = vx * fx + vy * fy + vz * fz;
+    const double d = eps * g2 * ((fx * fx + fy * fy + fz * fz) - vf * vf);
+    const double w = sp.w[i];
+    const double l = d > 0.0 ? log10(d) : -INFINITY;
+    long long b = l < lo ? -1 : (l >= hi ? bins : (long long)floor((l - lo) / (hi - lo) * bins));
+    if (b >= bins) b = l >= hi ? bins : bins - 1;  // l just below hi
+    atomicAdd(out + (b < 0 ? bins : (b >= bins ? bins + 1 : b)), w);
+    if (d > dmax) dmax = d;
+    wd += w * d;
+    ws += w;
+  }
+  s_max[threadIdx.x] = dmax;
+  s_sum[threadIdx.x] = wd;
+  s_w[threadIdx.x] = ws;
+  __syncthreads();
+  for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) {
+      s_max[threadIdx.x] = fmax(s_max[threadIdx.x], s_max[threadIdx.x + k]);
+      s_sum[threadIdx.x] += s_sum[threadIdx.x + k];
+      s_w[threadIdx.x] += s_w[threadIdx.x + k];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicMax(reinterpret_cast<unsigned long long*>(out + bins + 2),
+              (unsigned long long)__double_as_longlong(s_max[0]));
+    atomicAdd(out + bins + 3, s_sum[0]);
+    atomicAdd(out + bins + 4, s_w[0]);
+  }
+}
+
 }  // namespace pic

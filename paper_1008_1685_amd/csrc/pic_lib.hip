@@ -1228,6 +1228,34 @@ pic_status pic_spectrum(pic_run* r, int32_t bins, double e_max, double* host_his
   return PIC_OK;
 }
 
+pic_status pic_friction(pic_run* r, int32_t bins, double log10_lo, double log10_hi, double* host_hist,
+                        double* host_stats, void* stream) {
+  if (!r || !host_hist || !host_stats || bins < 1 || bins > kMaxSpectrumBins - 5 ||
+      !(log10_hi > log10_lo) || !std::isfinite(log10_lo) || !std::isfinite(log10_hi))
+    return fail(PIC_EINVAL, "bad friction arguments");
+  if (r->batch) return fail(PIC_EBUSY, "run is stepped by a batch; release it first");
+  hipStream_t s = S(stream);
+  double* out = reinterpret_cast<double*>(r->hist);  // the spectrum's counters, as FP64 sums
+  HIP_TRY(hipMemsetAsync(out, 0, (bins + 5) * sizeof(double), s));
+  const int p = (int)(r->step & 1);
+  if (r->d.prec == PIC_FP32)
+    hipLaunchKernelGGL(k_friction<float>, dim3(1024), dim3(256), 0, s, dev<float>(r->sp[0][r->pp]),
+                       fdev<float>(r, p), r->count + 2 * r->pp, out, bins, log10_lo, log10_hi, r->d.eps);
+  else
+    hipLaunchKernelGGL(k_friction<double>, dim3(1024), dim3(256), 0, s, dev<double>(r->sp[0][r->pp]),
+                       fdev<double>(r, p), r->count + 2 * r->pp, out, bins, log10_lo, log10_hi, r->d.eps);
+  HIP_TRY(hipGetLastError());
+  std::vector<double> h(bins + 5);
+  HIP_TRY(hipMemcpyAsync(h.data(), out, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int b = 0; b < bins; ++b) host_hist[b] = h[b];
+  host_stats[0] = h[bins + 2];
+  host_stats[1] = h[bins + 4] > 0 ? h[bins + 3] / h[bins + 4] : 0.0;
+  host_stats[2] = h[bins];
+  host_stats[3] = h[bins + 1];
+  return PIC_OK;
+}
+
 pic_status pic_track(const pic_wave* wave, int32_t scheme, int32_t rr, int32_t precision,
                      double lambda_um, double dt, double t0, int64_t steps, int64_t n, double* d_x,
                      double* d_ux, double* d_uy, double* d_uz, void* stream) {

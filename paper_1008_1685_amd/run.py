@@ -227,6 +227,18 @@ class Run:
                 "pic_spectrum")
         return h
 
+    def friction(self, bins: int, log10_lo: float, log10_hi: float):
+        """Friction coefficient d of every electron (Eq. (damping)): its
+        histogram in log10 d (electron weight per bin) and dict(max, mean,
+        below, above) (mean weighted; below/above: weight outside the range)."""
+        h = np.zeros(bins, np.float64)
+        st = np.zeros(4, np.float64)
+        N.check(self.lib.pic_friction(self._h, int(bins), float(log10_lo), float(log10_hi),
+                                      h.ctypes.data_as(C.POINTER(C.c_double)),
+                                      st.ctypes.data_as(C.POINTER(C.c_double)), self._stream()),
+                "pic_friction")
+        return h, dict(max=st[0], mean=st[1], below=st[2], above=st[3])
+
     def spectrum_static(self, bins: int, e_max_mev: float) -> np.ndarray:
         """As spectrum(), through the entry point that keeps its counters in
         the library's fixed device array (no device memory of its own)."""

@@ -382,3 +382,43 @@ def test_non_finite_momentum_is_flagged_and_dropped():
         run.diag()
     d = run.diag(allow_nonfinite=True)
     assert d["nonfinite"] == 1 and d["n_alive"] == (999, 1000)
+
+
+# --------------------------------------------------------------------------- friction coefficient
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_friction_coefficient_matches_oracle(precision):
+    # Eq. (damping) for every electron of a random state: the oracle gathers
+    # the same fields at the same positions and evaluates d in FP64
+    from oracle import pusher
+
+    cfg = preset("c1", box_lambda=5.0, x_foil=1.0, precision=precision)
+    sim = _oracle_for(cfg)
+    n = sim.nx
+    rdt = np.float32 if precision == "fp32" else np.float64
+    f = random_fields(41, n, 300.0)
+    pe = random_particles(42, 30000, 0, n, sim.w_ref, u_lo=1e-2, u_hi=1e3)
+    pi = random_particles(43, 1000, 0, n, sim.w_ref, u_hi=10.0)
+    run = _run(cfg, capacity=30000)
+    run.set_state({0: pe, 1: pi}, fields=f, step=0)
+    bins, lo, hi = 120, -3.0, 2.5
+    h, st = run.friction(bins, lo, hi)
+    sim = _oracle_for(cfg, f)
+    E, B = sim.gather(pe["cell"] + pe["off"])
+    u = np.stack([pe["ux"], pe["uy"], pe["uz"]], 1)
+    eps = pusher.rr_coefficient(cfg["lambda_um"])
+    d_exp, d = pusher.damping(E, B, u, eps)
+    w = pe["w"]
+    assert st["max"] == pytest.approx(d.max(), rel=1e-9)
+    assert st["mean"] == pytest.approx(np.sum(w * d) / np.sum(w), rel=1e-9)
+    with np.errstate(divide="ignore"):
+        l = np.where(d > 0, np.log10(np.where(d > 0, d, 1.0)), -np.inf)
+    below, above = l < lo, l >= hi
+    assert st["below"] == pytest.approx(w[below].sum(), rel=1e-12, abs=1e-300)
+    assert st["above"] == pytest.approx(w[above].sum(), rel=1e-12, abs=1e-300)
+    ref, _ = np.histogram(l[~below & ~above], bins=bins, range=(lo, hi), weights=w[~below & ~above])
+    # particles within rounding of a bin edge may land on either side
+    edge = np.abs((l - lo) / (hi - lo) * bins - np.rint((l - lo) / (hi - lo) * bins)) < 1e-9
+    assert np.sum(np.abs(h - ref)) <= 2 * w[edge].sum() + 1e-9 * w.sum()
+    assert h.sum() + st["below"] + st["above"] == pytest.approx(w.sum(), rel=1e-12)
+    assert st["below"] > 0 and st["above"] > 0 and h.sum() > 0.5 * w.sum()
+    assert np.allclose(d_exp, d, rtol=1e-6, atol=1e-9 * d.max())  # the paper's two forms agree

@@ -113,6 +113,32 @@ def test_worked_example(precision):
     assert abs(xaf - xar) / abs(xar) < 1e-8
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_worked_example_momentum_phase_error(precision):
+    # Section 3: p_x lags the exact orbit by about 0.1 (2 pi / omega) after
+    # 500 / omega; the lag of the last 1,200 steps, sampled every 10
+    g = json.load(open(os.path.join(GOLDEN, "worked_example.json")))
+    wave = analytic.MonochromaticWave(g["a0"])
+    eps = pusher.rr_coefficient(g["lambda_um"])
+    orb = analytic.PlaneWaveOrbit(wave, np.array([g["p_x0"], 0, 0]), eps=eps, phi_span=4000.0)
+    dt = g["dt"]
+    n = int(round(g["t_end"] / dt))
+    _, uh, _ = orb.at_time(-0.5 * dt)
+    k0 = n - 1200
+    x, u = _track([0.0], [uh], g["a0"], dt=dt, steps=k0, precision=precision, lambda_um=g["lambda_um"])
+    t, px = [], []
+    for k in range(k0, n, 10):
+        x, u = _track(x, u, g["a0"], dt=dt, steps=10, t0=k * dt, precision=precision,
+                      lambda_um=g["lambda_um"])
+        t.append((k + 9.5) * dt)
+        px.append(u[0, 0])
+    tau = analytic.px_time_lag(orb, t, px)
+    print(f"[{precision}] p_x phase error {tau:.3f} / omega = {abs(tau) / (2 * np.pi):.3f} periods "
+          f"(Section 3: about {g['px_phase_error_reported_periods']})", flush=True)
+    assert abs(tau) / (2 * np.pi) <= g["px_phase_error_reported_periods"]
+    assert abs(tau) > 1e-2
+
+
 def test_rk4_matches_the_oracle_comparator_and_converges_at_fourth_order():
     wave = analytic.MonochromaticWave(**WAVE)
     u0 = np.array([-8.0, 2.0, -1.0])

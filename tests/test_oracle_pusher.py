@@ -171,6 +171,34 @@ def test_worked_example_displacement_error():
     assert u[0] > 0 and xa > 0
 
 
+def test_worked_example_momentum_phase_error():
+    # Section 3's other figure for the same run: the longitudinal momentum
+    # lags the exact one by about 0.1 (2 pi / omega) after 500 / omega.  The
+    # lag is the time shift that best maps the last 1,200 steps of p_x onto
+    # the exact orbit; the helper finds a planted shift exactly
+    g = json.load(open(os.path.join(GOLDEN, "worked_example.json")))
+    wave = analytic.MonochromaticWave(g["a0"])
+    eps = pusher.rr_coefficient(g["lambda_um"])
+    orb = analytic.PlaneWaveOrbit(wave, np.array([g["p_x0"], 0, 0]), eps=eps, phi_span=4000.0)
+    dt = g["dt"]
+    n = int(round(g["t_end"] / dt))
+    _, u, _ = orb.at_time(-0.5 * dt)
+    x = np.zeros(3)
+    t, px = [], []
+    for k in range(n):
+        E, B = wave.fields(x[0], k * dt)
+        u, _ = pusher.push(u, E, B, -1.0, dt, eps, True)
+        x = x + dt * u / np.sqrt(1 + u @ u)
+        if k >= n - 1200 and k % 10 == 0:
+            t.append((k + 0.5) * dt)  # u^{k+1/2} after push k
+            px.append(u[0])
+    tau = analytic.px_time_lag(orb, t, px)
+    assert abs(tau) / (2 * np.pi) <= g["px_phase_error_reported_periods"]
+    assert abs(tau) > 1e-2  # the error is resolved, not rounding
+    planted = [orb.at_time(ti + 0.3)[1][0] for ti in t[::4]]
+    assert analytic.px_time_lag(orb, t[::4], planted) == pytest.approx(0.3, abs=1e-6)
+
+
 def test_radiative_cooling_in_uniform_b():
     # gamma(t) = coth(eps B^2 t + atanh(1/gamma0)); amplified eps
     eps, Bz, g0, t_end = 1e-4, 100.0, 50.0, 1.5
