@@ -256,6 +256,34 @@ def side_by_side_c2(warmup=3200, steps=2000):
     return out
 
 
+def small_runs():
+    """Whole runs of the small workloads through pic_step (two sort intervals
+    per graph replay): c1 (12,800 particles, 2,000 cells, 6,000 steps) and
+    c1w (102,400 particles), wall clock from the first step to the last;
+    launch latency, not bandwidth, bounds them."""
+    import torch
+
+    from paper_1008_1685_amd import Run
+    from workloads import periods_to_steps, preset
+
+    out = {}
+    for name in ("c1", "c1w"):
+        cfg = preset(name)
+        n = periods_to_steps(cfg)
+        run = Run(cfg)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run.step(n)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        d = run.diag()
+        pushes = 0.5 * (sum(run.get_info()["n_init"]) + sum(d["n_alive"])) * n  # (few leave)
+        out[name] = dict(pushes_per_s=pushes / dt, us_per_step=dt / n * 1e6, steps=n,
+                         particles=int(sum(run.get_info()["n_init"])), alive_end=list(d["n_alive"]))
+        run.close()
+    return out
+
+
 def cpu_baseline(cfg, state, budget_s=20.0, max_steps=12):
     """The FP64 oracle, as is, on a bounded sample of the same workload: a few
     steps from the state at which the GPU's timed window starts (particles,
@@ -537,6 +565,7 @@ def main():
         variants["steps"] = side
         line["c3_variants"] = variants
         line["plain_method_scale"] = side_by_side_c2()
+        line["small_runs"] = small_runs()
         line["pic2d"] = bench_2d()
         line["cpu_baseline"] = cpu_baseline(cfg, res["state"])
     if not args.no_serve:

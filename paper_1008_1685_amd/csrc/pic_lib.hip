@@ -244,20 +244,29 @@ constexpr size_t kNoEvent = ~(size_t)0;
 // Events for a sampled launch: the kernel launch itself records them at its
 // start and end (hipExtLaunchKernel), so the measured time is the kernel's
 // execution without the queue time of separate event packets.
+// The ring of event pairs, created once, when timing is switched on (not at
+// the first sampled launch, where creating them would fall inside the timed
+// stretch).
+template <class Run>
+pic_status ev_create(Run* r) {
+  if (!r->ev.empty()) return PIC_OK;
+  r->ev.resize(512);
+  for (auto& e : r->ev) {
+    HIP_TRY(hipEventCreate(&e.a));
+    HIP_TRY(hipEventCreate(&e.b));
+    e.used = false;
+  }
+  return PIC_OK;
+}
+
 template <class Run>
 pic_status ev_pick(Run* r, int kind, size_t* slot, hipEvent_t* a, hipEvent_t* b) {
   *slot = kNoEvent;
   *a = *b = nullptr;
   if (!r->timing) return PIC_OK;
   if (r->seen[kind]++ % r->timing) return PIC_OK;  // not sampled
-  if (r->ev.empty()) {
-    r->ev.resize(512);
-    for (auto& e : r->ev) {
-      HIP_TRY(hipEventCreate(&e.a));
-      HIP_TRY(hipEventCreate(&e.b));
-      e.used = false;
-    }
-  }
+  pic_status ps = ev_create(r);
+  if (ps) return ps;
   TimingRec& e = r->ev[r->ev_next];
   if (e.used) {  // ring full: fold the oldest record in
     HIP_TRY(hipEventSynchronize(e.b));
@@ -1320,6 +1329,10 @@ pic_status pic_check_rounding(uint32_t first, uint32_t count, unsigned long long
 pic_status pic_timing_enable(pic_run* r, int32_t period) {
   if (!r) return fail(PIC_EINVAL, "null run");
   if (period < 0) return fail(PIC_EINVAL, "negative timing period");
+  if (period) {
+    pic_status ps = ev_create(r);
+    if (ps) return ps;
+  }
   r->timing = period;
   for (auto& k : r->seen) k = 0;
   return PIC_OK;

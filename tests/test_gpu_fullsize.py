@@ -1,5 +1,6 @@
 """Parity at the full workload sizes, in the launch configuration bench.py
-times: the precision-form laser-foil run (20,000 cells, 1e7 particles) and
+times: the precision-form laser-foil run (20,000 cells, 1e7 particles; LP and
+CP at a0 = 500 and 200) and
 the stress run (80,000 cells, 2e8 particles), each stepped into the
 laser-foil interaction.  The oracle checks sampled particles one by one (one
 push from the run's own fields, then the contract move from the stored
@@ -122,3 +123,10 @@ def test_precision_form_full_size_step_matches_oracle():
 def test_stress_form_full_size_step_matches_oracle():
     # 2e8 particles, 80,000 cells, a0 = 800; the pulse reaches the foil after 6,400 steps
     _full_size_case(preset("c5"), steps=6417, sample=200_000, continuity=True)
+
+
+@pytest.mark.parametrize("pol,a0", [("CP", 500.0), ("CP", 200.0), ("LP", 200.0)])
+def test_precision_form_variants_full_size_step_matches_oracle(pol, a0):
+    # the precision-form workload's other polarisation and amplitude (Section 4
+    # compares LP and CP), at 10 periods, in the interaction
+    _full_size_case(preset("c3", pol=pol, a0=a0), steps=4033, sample=200_000, continuity=True)

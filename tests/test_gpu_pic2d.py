@@ -9,7 +9,8 @@ expected value comes from ``oracle``.  Tolerances:
   max(|u_old|, |u_L|, |u_new|, |dt q E / m|, |RR increment|, 1e-2); FP64 1e-12;
 * one field step (both field kernels, tiles and column strips): 1e-6 of the
   field scale in FP32 (rounding of the update), 1e-12 in FP64;
-* whole runs: each energy term within 1e-3 of the injected energy.
+* whole runs: the balance within 1e-3 of the injected energy; each energy term
+  within 1e-3 of it, or of its own size plus the oracle's seed spread.
 """
 import numpy as np
 import pytest
@@ -295,22 +296,35 @@ def test_sort_orders_by_cell_block_and_keeps_every_particle():
 @pytest.mark.parametrize("precision,kernel", [("fp32", "strips"), ("fp64", "strips"),
                                               ("fp32", "tiles")])
 def test_laser_foil_run_matches_oracle_budget(precision, kernel):
+    # against the oracle's run of the same seed (tests/golden/make_d1_reference.py,
+    # seeds 0-3): the balance within 1e-3 of the injected energy; each term
+    # within 1e-3 of the injected energy, and within 1e-3 of its own size
+    # plus the oracle's seed-to-seed spread of that term where that is
+    # tighter (the electron energy, ~1% of the injected energy, spreads by
+    # ~5% between seeds; the ion energy by ~0.5%)
+    import json
+    import os
+
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "d1_reference.json")))
     cfg = preset2d("d1", precision=precision, field_kernel=kernel)
-    sim = opic2d.Pic2D(cfg)
-    steps = 384  # 6 periods: the pulse (3 + 3 periods) reaches the foil at 4
+    steps = ref["steps"]
     run = _run(cfg)
     run.step(steps)
     d = run.diag()
-    sim.run(steps)
-    o = sim.diag()
-    assert o["K_e"] > 1e-3 * o["E_in"]  # the foil has been hit
-    for k in ("U_Ex", "U_Et", "U_B", "K_e", "K_i", "E_rad", "E_in", "E_out_left", "E_out_right",
-              "E_esc"):
-        assert abs(d[k] - o[k]) <= 1e-3 * o["E_in"], (k, d[k], o[k])
-    assert abs(d["balance"]) <= 2e-2 * o["E_in"]
+    o = ref["seeds"][str(cfg["seed"])]
+    e_in = o["E_in"]
+    assert d["E_in"] == pytest.approx(e_in, rel=1e-6)
+    assert o["K_e"] > 1e-3  # the foil has been hit
+    for k in ("U_Ex", "U_Et", "U_B", "K_e", "K_i", "E_rad", "E_out_left", "E_out_right", "E_esc"):
+        spread = float(np.ptp([r[k] for r in ref["seeds"].values()]))
+        tol = min(1e-3, 1e-3 * abs(o[k]) + spread) + 1e-12
+        print(f"[{precision} {kernel}] {k}: GPU {d[k] / e_in:.6f} oracle {o[k]:.6f} tol {tol:.2e}",
+              flush=True)
+        assert abs(d[k] / e_in - o[k]) <= tol, (k, d[k] / e_in, o[k], tol)
+    assert abs(d["balance"] / e_in - o["balance"]) <= 1e-3
     assert d["gauss_int"] == 0
     assert d["gauss"] < (1e-3 if precision == "fp32" else 1e-9) * cfg["n0"]
-    assert d["n_alive"] == tuple(sim.sp[s]["xi"].size for s in range(2))
+    assert list(d["n_alive"]) == o["n_alive"]
 
 
 # --------------------------------------------------------------------------- full size

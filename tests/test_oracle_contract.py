@@ -89,3 +89,28 @@ def test_integer_deposit_matches_double_precision_deposit():
     assert np.max(np.abs(Jy * s / sim.dx - J[1])) < 30 * 2.0 ** -22 * scale_y
     assert np.max(np.abs(Jz * s / sim.dx - J[2])) < 30 * 2.0 ** -22 * scale_y
     assert np.max(np.abs(J[1])) > 1e3 * 2.0 ** -22 * scale_y
+
+
+def test_charge_weight_of_non_reference_weights():
+    # the contract's charge weight is the particle weight in units of
+    # w_ref / 256, rounded to the nearest integer: qw / 256 lies within half
+    # a unit (2^-9) of w / w_ref, carries the species' sign, and is exact
+    # (+-256) at the reference weight; rounding goes to the nearest integer
+    # on both sides of a half-unit boundary
+    rng = np.random.default_rng(3)
+    for w_ref in (0.0123, 1.7, 56.25):
+        w = (w_ref * rng.uniform(0.01, 40.0, 20000)).astype(np.float32)
+        for Z in (-1, 1):
+            qw = contract.charge_weight(w, w_ref, Z)
+            assert qw.dtype == np.int64
+            ratio = w.astype(np.float64) / w_ref
+            # float32 arithmetic of w * (256 / w_ref): within half a unit plus
+            # the float32 rounding of the product
+            assert np.all(np.abs(Z * qw / 256.0 - ratio) <= 0.5 / 256.0 + 2.0 ** -22 * ratio)
+            assert np.all(np.sign(qw) == Z)
+        assert contract.charge_weight(np.float32(w_ref), w_ref, -1) == -256
+    # half-unit boundaries round to even like rint: 2.5 units -> 2, 3.5 units -> 4
+    w_ref = 256.0
+    assert contract.charge_weight(np.float32(2.5), w_ref, 1) == 2
+    assert contract.charge_weight(np.float32(3.5), w_ref, 1) == 4
+    assert contract.charge_weight(np.float32(3.25), w_ref, 1) == 3
