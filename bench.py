@@ -346,14 +346,14 @@ def serve_bench(n_runs=256, rate=20.0, seed=0, max_slots=64, budget_gb=64.0):
                 peak_resident_bytes=srv.peak_bytes, max_slots=max_slots, failed_checks=bad)
 
 
-def stress_bench(serve_kwargs, t_start=8.5, window=200, chunk=8, share=0.2):
-    """The stress run (2e8 particles, 80,000 cells, LP a0 = 800) on its own
-    stream: its throughput alone, then stepped by a second host thread while
-    the serving stream is served on the same GPU (latency under load).  Both
-    streams have the default priority; the stress thread keeps a duty cycle
-    of `share` (after a chunk of steps that took t it waits t (1 - share) /
-    share), which leaves the rest of the GPU time to the latency-bound
-    requests (share = 1: no throttling)."""
+def stress_bench(serve_kwargs, t_start=8.5, window=200, chunk=8, max_grid=512):
+    """The stress run (2e8 particles, 80,000 cells, LP a0 = 800), stepped from
+    the pulse's arrival at the foil on a stream of its own, its push and sort
+    passes split into launches of at most `max_grid` work-groups
+    (pic_set_max_grid; 0: whole passes): its throughput alone, then while a
+    second host thread steps it without pause and the serving stream is
+    served on the same GPU.  Both streams have the default priority; the
+    requests' kernels are dispatched between the stress run's pieces."""
     import threading
 
     import torch
@@ -364,6 +364,7 @@ def stress_bench(serve_kwargs, t_start=8.5, window=200, chunk=8, share=0.2):
     cfg = preset("c5")
     st = torch.cuda.Stream()
     run = Run(cfg, stream=st)
+    run.set_max_grid(max_grid)
     n = sum(run.get_info()["n_init"])
     warm = window_start(cfg, 0, t_start)  # the pulse reaches the foil after 8 periods
     run.step(warm)
@@ -377,12 +378,9 @@ def stress_bench(serve_kwargs, t_start=8.5, window=200, chunk=8, share=0.2):
 
     def loop():
         while not stop.is_set():
-            ta = time.perf_counter()
             run.step(chunk)
             st.synchronize()
             done[0] += chunk
-            if share < 1.0:
-                stop.wait((time.perf_counter() - ta) * (1.0 - share) / share)
 
     th = threading.Thread(target=loop, daemon=True)
     t1 = time.perf_counter()
@@ -398,9 +396,9 @@ def stress_bench(serve_kwargs, t_start=8.5, window=200, chunk=8, share=0.2):
     return dict(workload=f"c5: LP a0={cfg['a0']:g}, {run.info['n_init'][0] + run.info['n_init'][1]} particles, "
                          f"80000 cells, fp32 + compensated RR, stepped from step {warm} "
                          f"({warm / 800:.2f} periods, in the laser-foil interaction)",
-                pushes_per_s_alone=alone, duty_cycle=share, pushes_per_s_with_serving=n * done[0] / el,
-                steps_with_serving=done[0], gauss_int=d["gauss_int"],
-                serving_under_load=serving)
+                max_grid=max_grid, pushes_per_s_alone=alone,
+                pushes_per_s_with_serving=n * done[0] / el, steps_with_serving=done[0],
+                gauss_int=d["gauss_int"], serving_under_load=serving)
 
 
 def write_traffic(fetch, write, cfetch, cwrite, out_path, kernel="k_push", workload="c3",
@@ -448,8 +446,8 @@ def main():
                     help="skip the stress run and the serving measurement under its load")
     ap.add_argument("--stress-only", type=int, default=0, metavar="N",
                     help="only run the stress run with the first N serving requests beside it")
-    ap.add_argument("--stress-share", type=float, default=0.2,
-                    help="duty cycle of the stress run while requests are served (1: unthrottled)")
+    ap.add_argument("--stress-grid", type=int, default=512,
+                    help="work-groups per launch of the stress run's push and sort passes (0: whole)")
     ap.add_argument("--only-2d", action="store_true",
                     help="only run the 2D3V measurement (with --no-side-runs: without its RR-off "
                          "and FP64 runs)")
@@ -489,7 +487,7 @@ def main():
         print(json.dumps(dict(pic2d=bench_2d(side_runs=not args.no_side_runs))), flush=True)
         return
     if args.stress_only:
-        print(json.dumps(dict(stress=stress_bench(dict(n_runs=args.stress_only), share=args.stress_share))),
+        print(json.dumps(dict(stress=stress_bench(dict(n_runs=args.stress_only), max_grid=args.stress_grid))),
               flush=True)
         return
     cfg = preset(args.workload)
@@ -571,7 +569,7 @@ def main():
     if not args.no_serve:
         line["serving"] = serve_bench()
         if not args.no_stress:
-            line["stress"] = stress_bench(dict(), share=args.stress_share)
+            line["stress"] = stress_bench(dict(), max_grid=args.stress_grid)
     print(json.dumps(line), flush=True)
 
 

@@ -210,6 +210,14 @@ void pic_free(struct pic_run* run);
 /* Message of the last failed call on this thread ("" if none). */
 const char* pic_last_error(void);
 
+/* Bound the work-groups of one launch of the push and of the sort passes
+ * (0, the default: one launch per pass).  A run of 2e8 particles pushes in
+ * about 39,000 work-groups per step; split into launches of a few thousand,
+ * kernels that other streams enqueue meanwhile (small runs served beside
+ * it) are dispatched between the pieces instead of after the whole pass.
+ * Results do not change.  Host-only. */
+pic_status pic_set_max_grid(struct pic_run* run, int32_t max_workgroups);
+
 /* Stage entry points (one kernel each), for tests and profiling.  Async.
  *   pic_push_deposit: steps 1-5 for every particle; leaves J_int of this
  *     push in the run (readable with pic_get_state) and does not advance

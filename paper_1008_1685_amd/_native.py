@@ -276,6 +276,7 @@ SIGNATURES = {
                                       C.c_void_p]),
     "pic_friction": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.POINTER(C.c_double),
                                C.POINTER(C.c_double), C.c_void_p]),
+    "pic_set_max_grid": (C.c_int, [C.c_void_p, C.c_int32]),
     "pic_timing_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "pic_timing_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                   C.c_void_p]),
@@ -338,3 +339,4 @@ def check(status, where):
     if status != PIC_OK:
         msg = load().pic_last_error().decode(errors="replace")
         raise PicError(status, where, msg)
+

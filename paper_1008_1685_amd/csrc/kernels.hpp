@@ -116,6 +116,7 @@ struct PushArgs {
   R sw;                          // 256 / w_ref (charge-weight scale)
   int qw_ref[2];                 // charge weight of a particle of weight w_ref
   int ntiles;                    // tiles of both species
+  int tile0;                     // first tile of this launch (a step may be split over launches)
   // Cell range of every tile after the previous push (the particles' cells
   // now, as long as no sort or state change came between): with *pred_in
   // set, a tile sizes its current window from it instead of a pass over its
@@ -823,7 +824,7 @@ __device__ __forceinline__ void push_one_tile(const PushArgs<R>& a, int tile,
 template <typename R>
 __global__ PIC_PUSH_BOUNDS void k_push(PushArgs<R> a) {
   __shared__ unsigned long long lds[kLdsSlots];
-  push_one_tile<R, kPPT, kDepth>(a, (int)blockIdx.x, lds);
+  push_one_tile<R, kPPT, kDepth>(a, a.tile0 + (int)blockIdx.x, lds);
 }
 
 // the same push in tiles of kBatchTile (the whole tile's loads up front),
@@ -831,7 +832,7 @@ __global__ PIC_PUSH_BOUNDS void k_push(PushArgs<R> a) {
 template <typename R>
 __global__ PIC_PUSH_BOUNDS void k_push_small(PushArgs<R> a) {
   __shared__ unsigned long long lds[kLdsSlots];
-  push_one_tile<R, kBatchPPT, kBatchPPT>(a, (int)blockIdx.x, lds);
+  push_one_tile<R, kBatchPPT, kBatchPPT>(a, a.tile0 + (int)blockIdx.x, lds);
 }
 
 // ---------------------------------------------------------------- fields
@@ -1020,6 +1021,7 @@ struct SortArgs {
   int* cnt[2];          // [n] per-cell counts (zero on entry to k_sort_hist)
   int* cursor[2];       // [n] scatter cursors
   int blocks0;          // blocks of species 0 in hist / scatter grids
+  int blk0;             // first block of this launch (a pass may be split over launches)
   int nx;
   int comp;             // carry residuals of species 0
   int* pred;            // [2] the push's range-prediction flags, cleared: the order changes
@@ -1122,7 +1124,7 @@ __device__ __forceinline__ void sort_hist_block(const SortArgs<R>& p, int blk) {
 
 template <typename R>
 __global__ __launch_bounds__(kSortThreads) void k_sort_hist(SortArgs<R> p) {
-  sort_hist_block<R>(p, (int)blockIdx.x);
+  sort_hist_block<R>(p, p.blk0 + (int)blockIdx.x);
 }
 
 // inclusive prefix sum over the 64 lanes of a wave (all lanes active)
@@ -1293,7 +1295,7 @@ __device__ __forceinline__ void sort_scatter_block(const SortArgs<R>& p, int blk
 
 template <typename R>
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortArgs<R> p) {
-  sort_scatter_block<R>(p, (int)blockIdx.x);
+  sort_scatter_block<R>(p, p.blk0 + (int)blockIdx.x);
 }
 
 // ---------------------------------------------------------------- test electrons

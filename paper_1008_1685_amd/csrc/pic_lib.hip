@@ -163,6 +163,9 @@ struct pic_run {
   hipGraphExec_t step_graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   hipGraph_t step_graph_def[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   hipStream_t capture_stream = nullptr;  // a stream to record on; replays go to the caller's
+  // work-groups per launch of the push and sort passes (0: one launch per
+  // pass); a large run split this way lets other streams' kernels in between
+  int max_grid = 0;
   // timing: every timing-th launch of each kernel kind is bracketed by events
   int timing = 0;
   long long seen[3] = {0, 0, 0};
@@ -387,28 +390,39 @@ SortArgs<R> make_sort_args(const pic_run* r, int pp) {
 
 // Launches of one step's kernels.  `capture`: the launch is being recorded
 // into a graph (plain launches, no timing events).
+// Launches covering `total` work-groups: one, or pieces of at most max_grid.
+template <class F>
+void split_launch(int total, int max_grid, F&& launch) {
+  const int step = max_grid > 0 ? max_grid : total;
+  for (int b0 = 0; b0 < total; b0 += step) launch(b0, std::min(step, total - b0), b0 == 0, b0 + step >= total);
+}
+
 template <typename R>
 pic_status launch_push(pic_run* r, hipStream_t st, bool capture = false) {
-  const PushArgs<R> a = make_push_args<R>(r, r->pp, (int)(r->step & 1), r->push_tile);
+  PushArgs<R> a = make_push_args<R>(r, r->pp, (int)(r->step & 1), r->push_tile);
   if (a.ntiles == 0) return PIC_OK;
-  if (capture) {
-    if (r->push_tile == kBatchTile)
-      hipLaunchKernelGGL(k_push_small<R>, dim3(a.ntiles), dim3(kThreads), 0, st, a);
-    else
-      hipLaunchKernelGGL(k_push<R>, dim3(a.ntiles), dim3(kThreads), 0, st, a);
-    HIP_TRY(hipGetLastError());
-    return PIC_OK;
+  size_t slot = kNoEvent;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (!capture) {
+    pic_status ps = ev_pick(r, 0, &slot, &e0, &e1);
+    if (ps) return ps;
   }
-  size_t slot;
-  hipEvent_t e0, e1;
-  pic_status ps = ev_pick(r, 0, &slot, &e0, &e1);
-  if (ps) return ps;
-  if (r->push_tile == kBatchTile)
-    hipExtLaunchKernelGGL(k_push_small<R>, dim3(a.ntiles), dim3(kThreads), 0, st, e0, e1, 0, a);
-  else
-    hipExtLaunchKernelGGL(k_push<R>, dim3(a.ntiles), dim3(kThreads), 0, st, e0, e1, 0, a);
+  // the events span the pieces: start of the first, end of the last
+  split_launch(a.ntiles, r->max_grid, [&](int t0, int n, bool first, bool last) {
+    a.tile0 = t0;
+    hipEvent_t s0 = first ? e0 : nullptr, s1 = last ? e1 : nullptr;
+    const bool small = r->push_tile == kBatchTile;
+    if (capture && small)  // (recorded launches carry no events)
+      hipLaunchKernelGGL(k_push_small<R>, dim3(n), dim3(kThreads), 0, st, a);
+    else if (capture)
+      hipLaunchKernelGGL(k_push<R>, dim3(n), dim3(kThreads), 0, st, a);
+    else if (small)
+      hipExtLaunchKernelGGL(k_push_small<R>, dim3(n), dim3(kThreads), 0, st, s0, s1, 0, a);
+    else
+      hipExtLaunchKernelGGL(k_push<R>, dim3(n), dim3(kThreads), 0, st, s0, s1, 0, a);
+  });
   HIP_TRY(hipGetLastError());
-  ev_done(r, slot);
+  if (!capture) ev_done(r, slot);
   return PIC_OK;
 }
 
@@ -441,16 +455,25 @@ pic_status launch_sort(pic_run* r, hipStream_t st, bool capture = false) {
     if (ps) return ps;
   }
   // the events span the three passes: start of the histogram, end of the scatter
-  if (capture)
-    hipLaunchKernelGGL(k_sort_hist<R>, dim3(grid), dim3(kSortThreads), 0, st, p);
-  else
-    hipExtLaunchKernelGGL(k_sort_hist<R>, dim3(grid), dim3(kSortThreads), 0, st, e0, nullptr, 0, p);
+  SortArgs<R> q = p;
+  split_launch(grid, r->max_grid, [&](int b0, int n, bool first, bool) {
+    q.blk0 = b0;
+    if (capture)
+      hipLaunchKernelGGL(k_sort_hist<R>, dim3(n), dim3(kSortThreads), 0, st, q);
+    else
+      hipExtLaunchKernelGGL(k_sort_hist<R>, dim3(n), dim3(kSortThreads), 0, st, first ? e0 : nullptr,
+                            nullptr, 0, q);
+  });
   hipLaunchKernelGGL(k_sort_scan, dim3(2), dim3(1024), 0, st, r->cnt[0], r->cnt[1], r->cursor[0],
                      r->cursor[1], r->count + 2 * (r->pp ^ 1), r->d.nx);
-  if (capture)
-    hipLaunchKernelGGL(k_sort_scatter<R>, dim3(grid), dim3(kSortThreads), 0, st, p);
-  else
-    hipExtLaunchKernelGGL(k_sort_scatter<R>, dim3(grid), dim3(kSortThreads), 0, st, nullptr, e1, 0, p);
+  split_launch(grid, r->max_grid, [&](int b0, int n, bool, bool last) {
+    q.blk0 = b0;
+    if (capture)
+      hipLaunchKernelGGL(k_sort_scatter<R>, dim3(n), dim3(kSortThreads), 0, st, q);
+    else
+      hipExtLaunchKernelGGL(k_sort_scatter<R>, dim3(n), dim3(kSortThreads), 0, st, nullptr,
+                            last ? e1 : nullptr, 0, q);
+  });
   HIP_TRY(hipGetLastError());
   if (!capture) ev_done(r, slot);
   r->pp ^= 1;
@@ -1323,6 +1346,13 @@ pic_status pic_check_rounding(uint32_t first, uint32_t count, unsigned long long
   const unsigned blocks = std::min<unsigned>(8192u, (count + 255u) / 256u);
   hipLaunchKernelGGL(k_check_rounding, dim3(blocks), dim3(256), 0, S(stream), first, count, d_mismatches);
   HIP_TRY(hipGetLastError());
+  return PIC_OK;
+}
+
+pic_status pic_set_max_grid(pic_run* r, int32_t max_workgroups) {
+  if (!r || max_workgroups < 0) return fail(PIC_EINVAL, "null run or negative limit");
+  r->max_grid = max_workgroups;
+  drop_step_graphs(r);  // the recorded launches follow the limit
   return PIC_OK;
 }
 

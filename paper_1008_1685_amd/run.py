@@ -102,6 +102,11 @@ class Run:
     def sort(self):
         N.check(self.lib.pic_sort(self._h, self._stream()), "pic_sort")
 
+    def set_max_grid(self, max_workgroups: int):
+        """Split the push and sort passes into launches of at most
+        max_workgroups work-groups (0: one launch per pass)."""
+        N.check(self.lib.pic_set_max_grid(self._h, int(max_workgroups)), "pic_set_max_grid")
+
     # ------------------------------------------------------------ inspection
     def get_info(self) -> dict:
         o = N.PicInfo()

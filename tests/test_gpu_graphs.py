@@ -80,3 +80,23 @@ def test_graph_replays_match_kernel_by_kernel_steps(precision):
     g.step(200)
     _eager(e, 200, interval)
     _same(g.get_state(), e.get_state(), "after set_state")
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_split_launches_give_the_same_run(precision):
+    # the push and sort passes split into launches of 3 work-groups (graph
+    # replays and launch by launch) end in the state of whole-pass launches
+    from paper_1008_1685_amd import Run
+
+    cfg = preset("c1", ppc=64, x_foil=2.0, box_lambda=6.0, pol="LP", a0=300.0,
+                 precision=precision, sort_interval=16)
+    whole, split = Run(cfg), Run(cfg)
+    split.set_max_grid(3)
+    for n in (5, 300, 1, 1500):
+        whole.step(n)
+        split.step(n)
+        _same(whole.get_state(), split.get_state(), n)
+    dw, ds = whole.diag(), split.diag()
+    for k in ("E_in", "U_field", "gauss_int", "n_alive"):
+        assert dw[k] == ds[k], k
+    assert dw["E_rad"] == pytest.approx(ds["E_rad"], rel=1e-6)
