@@ -14,9 +14,10 @@ same configuration and seed as its reference.  The comparisons:
   1e-3 of it; a smaller term within 1e-3 of its own size plus twice the
   oracle's noise floor of that term at that step (the larger of its
   seed-to-seed spread and its response to a float32-rounded start), plus
-  1e-12 of the injected energy, below which a term is rounding noise (RR
-  before the pulse arrives, say, where FP32 partial sums round 1e-83 to
-  zero).  The small terms (the radiated energy of these circularly polarised
+  1e-10 of the injected energy, below which a term is rounding noise: RR
+  before the pulse arrives, where FP32 partial sums round 1e-83 to zero, or
+  the 2e-9 reflected at the entrance before the pulse reaches the foil,
+  which FP32 fields of the incident amplitude resolve to ~0.3%.  The small terms (the radiated energy of these circularly polarised
   runs, light leaving at the far end, escaped particles) move by 5-50%
   between runs: the light transmitted through the c1 foil (6e-5 of the
   injected energy) moves by up to 8% when only the start is rounded, more
@@ -110,7 +111,7 @@ def _figures(h, e_max):
 def _term_tol(ref_value, spread):
     if abs(ref_value) >= 1e-3:
         return 1e-3
-    return 1e-3 * abs(ref_value) + 2.0 * spread + 1e-12
+    return 1e-3 * abs(ref_value) + 2.0 * spread + 1e-10
 
 
 def _check_run(name, seed, rows, ref, spread, terms_per_run=True):
@@ -201,3 +202,69 @@ def test_c1_whole_runs_match_the_oracle(precision):
           f"central-80% width GPU {g_w.round(1)} oracle {o_w.round(1)} MeV", flush=True)
     assert abs(g_pk.mean() - o_pk.mean()) <= 0.01 * o_pk.mean()
     assert abs(g_w.mean() - o_w.mean()) <= 0.01 * o_w.mean()
+
+
+def _c2_refs(rr):
+    out = {}
+    for f in sorted(glob.glob(os.path.join(GOLD, "c2_reference", f"rr{rr}_seed*.json"))):
+        r = json.load(open(f))
+        out[(r["seed"], bool(r.get("f32_start", False)))] = r
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("rr", [1, 0])
+def test_c2_whole_runs_match_the_oracle(precision, rr):
+    # the plain method at scale (LP a0 = 300, 12,000 cells, 4e5 particles,
+    # 24,000 steps), RR on and off, the FP64 and FP32 paths, 3 seeds.  LP
+    # heats the electrons chaotically: the oracle's runs differ by 1-2% of the
+    # injected energy in single terms and by 30% in the spectral peak (which
+    # jumps between bunch and tail), so only the balance can be held run by
+    # run; terms and spectrum are compared as seed means within 1e-3 (1%)
+    # plus twice the oracle's noise floor (its seed spread, or its response to
+    # a float32-rounded start where measured, the largest from the pulse's
+    # arrival at the foil on)
+    refs = _c2_refs(rr)
+    seeds = sorted(s for s, f in refs if not f)
+    assert len(seeds) >= 3
+    # the noise floor of a term: the largest of its per-step floors from the
+    # pulse's arrival on (the spread of three seeds at one step can be small
+    # by chance; the chaotic state's spread is not)
+    spread = _spread(refs)
+    arrive = next(i for i, r in enumerate(refs[(seeds[0], False)]["series"]) if r["step"] > 3200)
+    for k in TERMS:
+        late = max(row[k] for row in spread[arrive:])
+        for row in spread[arrive:]:
+            row[k] = late
+    g_rows, g_spec, o_spec = [], [], []
+    for seed in seeds:
+        ref = refs[(seed, False)]
+        cfg = preset("c2", precision=precision, seed=seed, rr=bool(rr))
+        rows, h = _gpu_run(cfg, ref["every"], ref["steps"], (ref["bins"],), ref["e_max_mev"])
+        g_rows.append(_check_run("c2", seed, rows, ref, spread, terms_per_run=False))
+        g_spec.append(_figures(h[ref["bins"]], ref["e_max_mev"]))
+        edges = np.linspace(0.0, ref["e_max_mev"], ref["bins"] + 1)
+        oh = np.array(ref["hist"])
+        o_spec.append((spectrum.peak_and_fwhm(oh, edges)[0], spectrum.width80(oh, edges)))
+        print(f"[c2 rr={rr} {precision} seed {seed}] final balance GPU "
+              f"{rows[-1]['balance'] / rows[-1]['E_in']:.2e} oracle {ref['series'][-1]['balance']:.2e}; "
+              f"peak {g_spec[-1][0]:.1f} (oracle {o_spec[-1][0]:.1f}) MeV, central-80% width "
+              f"{g_spec[-1][1]:.1f} (oracle {o_spec[-1][1]:.1f}) MeV", flush=True)
+    worst = {k: 0.0 for k in TERMS}
+    for i in range(len(spread)):
+        for k in TERMS:
+            gm = np.mean([g[i][k] for g in g_rows])
+            om = np.mean([refs[(s, False)]["series"][i][k] for s in seeds])
+            worst[k] = max(worst[k], abs(gm - om))
+            tol = (1e-3 if abs(om) >= 1e-3 else 1e-3 * abs(om)) + 2.0 * spread[i][k] + 1e-10
+            assert abs(gm - om) <= tol, (i, k, gm, om, tol)
+    print(f"[c2 rr={rr} {precision}] largest |mean GPU - mean oracle| (fraction of E_in):",
+          {k: f"{v:.2e}" for k, v in worst.items()}, flush=True)
+    g_spec, o_spec = np.array(g_spec), np.array(o_spec)
+    floor = np.ptp(o_spec, axis=0) / o_spec.mean(axis=0)  # relative seed spread of peak, width
+    for j, name in enumerate(("peak", "central-80% width")):
+        rel = abs(g_spec[:, j].mean() / o_spec[:, j].mean() - 1.0)
+        print(f"[c2 rr={rr} {precision}] mean {name}: GPU {g_spec[:, j].mean():.1f} oracle "
+              f"{o_spec[:, j].mean():.1f} MeV ({100 * rel:.1f}%; seed spread {100 * floor[j]:.0f}%)",
+              flush=True)
+        assert rel <= max(0.01, 2.0 * floor[j])
