@@ -116,18 +116,23 @@ def time_run(cfg, steps, warmup, diag_every, timing=TIMING_PERIOD, t_start=T_STA
         torch.cuda.synchronize()
         return time.perf_counter() - t
 
+    # host-side work (diagnostics, the state copy) comes before the last untimed
+    # steps, so the device is busy again when the window opens
     if sort_cost:
         run.step(s0 - m)
+        d0 = run.diag()
+        state = run.get_state() if keep_state else None
         t_plain = wall(m)   # [s0 - m, s0): no sort
         t_sort = wall(m)    # [s0, s0 + m): the sort at s0 and the push after it
         c_sort = max(t_sort - t_plain, 0.0)
         start = s0 + m
     else:
-        run.step(s0)
+        run.step(s0 - m)
+        d0 = run.diag()
+        state = run.get_state() if keep_state else None
+        run.step(m)
         c_sort = None
         start = s0
-    d0 = run.diag()
-    state = run.get_state() if keep_state else None
     torch.cuda.synchronize()
     run.timing(timing)
     t0 = time.perf_counter()

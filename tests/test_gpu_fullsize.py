@@ -54,6 +54,10 @@ def _sampled_push(cfg, run, fields, before, after, s, tol):
     scale = np.maximum.reduce([nrm(u0), nrm(uL), nrm(un), abs(sim.qm[s]) * sim.dt * nrm(E),
                                nrm(un - uL), np.full(len(u0), 1e-2)])
     err = float((nrm(ug - un) / scale).max())
+    err14 = nrm(ug - un) / np.maximum(nrm(un), 1e-2)
+    print(f"[species {s}] {len(u0)} sampled pushes: worst |du| / step scale {err:.2e} (tolerance "
+          f"{tol:.0e}); worst |du| / max(|u_oracle|, 1e-2) {err14.max():.2e}, within {tol:.0e} for "
+          f"{100 * np.mean(err14 <= tol):.4f}%", flush=True)
     assert err <= tol, err
     # contract move from the stored momentum: bit-exact cell and offset
     c1, o1, *_ = contract.move(before["cell"][alive], before["off"][alive],
