@@ -322,10 +322,12 @@ def cpu_baseline(cfg, state, budget_s=20.0, max_steps=12):
                        "where the timed window starts; numpy, one thread")
 
 
-def serve_bench(n_runs=256, rate=20.0, seed=0, max_slots=64, budget_gb=64.0):
+def serve_bench(n_runs=256, rate=20.0, seed=0, max_slots=64, budget_gb=64.0, persistent=False):
     """Serving form: a Poisson stream of independent laser-foil requests
     (a0, polarisation, density, thickness, size and length randomised),
-    continuously batched; latency = completion - arrival."""
+    continuously batched; latency = completion - arrival.  persistent: each
+    quantum's steps as one persistent launch rather than a push and a field
+    launch per step."""
     import numpy as np
 
     from paper_1008_1685_amd.serve import Server, run_steps
@@ -336,7 +338,8 @@ def serve_bench(n_runs=256, rate=20.0, seed=0, max_slots=64, budget_gb=64.0):
                 for r in reqs)
     max_c = max(round(r["cfg"]["box_lambda"] * r["cfg"]["cells_per_lambda"]) for r in reqs)
     srv = Server(budget_bytes=int(budget_gb * 2 ** 30), max_slots=max_slots,
-                 max_particles=max_slots * max_p, max_cells=max_slots * (max_c + 8))
+                 max_particles=max_slots * max_p, max_cells=max_slots * (max_c + 8),
+                 persistent=persistent)
     t0 = time.perf_counter()
     recs = srv.serve(reqs)
     wall = time.perf_counter() - t0
@@ -348,7 +351,9 @@ def serve_bench(n_runs=256, rate=20.0, seed=0, max_slots=64, budget_gb=64.0):
                 requests=len(recs), p50_s=float(np.percentile(lat, 50)),
                 p99_s=float(np.percentile(lat, 99)), mean_s=float(lat.mean()), wall_s=wall,
                 pushes=float(pushes), pushes_per_s=pushes / wall,
-                peak_resident_bytes=srv.peak_bytes, max_slots=max_slots, failed_checks=bad)
+                peak_resident_bytes=srv.peak_bytes, max_slots=max_slots, failed_checks=bad,
+                launch_form="one persistent launch per quantum" if persistent
+                else "a push and a field launch per step")
 
 
 def stress_bench(serve_kwargs, t_start=8.5, window=200, chunk=8, max_grid=512):
@@ -460,6 +465,8 @@ def main():
                     help="with --write-traffic: the 2D push kernel on d2 (profiles/traffic_d2.json)")
     ap.add_argument("--serve-only", type=int, default=0, metavar="N",
                     help="only run the serving measurement, on the first N requests")
+    ap.add_argument("--serve-persistent", action="store_true",
+                    help="with --serve-only: each quantum's steps as one persistent launch")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
     ap.add_argument("--write-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
                                                          "COPY_WRITE_CSV"),
@@ -486,7 +493,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.serve_only:
-        print(json.dumps(dict(serving=serve_bench(n_runs=args.serve_only))), flush=True)
+        print(json.dumps(dict(serving=serve_bench(n_runs=args.serve_only,
+                                                  persistent=args.serve_persistent))), flush=True)
         return
     if args.only_2d:
         print(json.dumps(dict(pic2d=bench_2d(side_runs=not args.no_side_runs))), flush=True)

@@ -348,8 +348,11 @@ pic_status pic_timing_read(struct pic_run* run, double ms[3], int64_t launches[3
  * uneven size).  A batch keeps a device table of up to max_slots resident
  * runs and advances all of them with the same launches: per quantum
  * (= the runs' sort_interval steps) one sort stage (hist, scan, scatter) and
- * then, per step, one push-deposit, one field and one tick launch whose
- * work-groups are spread over the runs' tiles.  Each run derives its buffer
+ * then, per step, one push-deposit and one field launch whose work-groups
+ * are spread over the runs' tiles (the field launch also advances each
+ * run's step counter), or, in the persistent form (pic_batch_set_persistent),
+ * one launch that runs all the quantum's steps with grid-wide barriers
+ * between the passes.  Each run derives its buffer
  * parities, sort schedule and laser clock from its own device step counter,
  * so the quantum is captured once into a HIP graph and replayed while runs
  * join and leave; every run executes exactly the kernels it would execute
@@ -392,8 +395,23 @@ pic_status pic_batch_fits(const pic_batch* b, const pic_config* cfg, int32_t* no
 pic_status pic_batch_step(pic_batch* b, int32_t n_quanta, void* stream);
 
 /* Copy every slot's current step to steps[max_slots] (-1 for free slots).
- * Blocking. */
+ * PIC_EHIP if a persistent launch timed out in a grid barrier (its steps
+ * are not valid; the batch stays in error).  Blocking. */
 pic_status pic_batch_poll(pic_batch* b, int64_t* steps, void* stream);
+
+/* Choose how a quantum's steps are launched: on = 0 (default), one
+ * push-deposit and one field launch per step, 2 x quantum launches after the
+ * sort; on = 1, one persistent launch per quantum whose work-groups (as many
+ * as the work needs, no more than fit the device at once) loop over the
+ * push tiles and then the field chunks of every run, with a grid-wide
+ * barrier after each pass, and advance the step counters once at the end.
+ * Both forms execute the same per-particle and per-node arithmetic, so a
+ * run's fields, integer currents and particles are bit-identical either way
+ * (Section 2 leapfrog cycle: gather-push-deposit, then the field advance).
+ * The persistent form needs max_slots <= 128 (PIC_EINVAL otherwise).  Takes
+ * effect at the next pic_batch_step (the graph is captured again).
+ * Host-only. */
+pic_status pic_batch_set_persistent(pic_batch* b, int32_t on);
 
 /* Detach the run of `slot` (its state stays in its workspace; pic_diag and
  * the other single-run calls work again).  Blocking. */

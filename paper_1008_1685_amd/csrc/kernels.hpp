@@ -57,6 +57,12 @@ constexpr int kLdsSlots = PIC_PUSH_LDS_SLOTS;  // 64-bit LDS current accumulator
 constexpr int kDepth = PIC_PUSH_DEPTH;        // particles per thread whose loads are in flight
 constexpr int kRingUnroll = PIC_RING_UNROLL;  // ring turns per loop iteration (renames, no copies)
 constexpr int kLanes = 64;            // wavefront width
+#ifndef PIC_STEPS_MIN_WAVES
+#define PIC_STEPS_MIN_WAVES 4  // waves per SIMD the persistent batched-step kernel is compiled for
+#endif
+#ifndef PIC_STEPS_BLOCKS_PER_CU
+#define PIC_STEPS_BLOCKS_PER_CU 0  // work-groups per CU of the persistent launch (0: as many as fit)
+#endif
 #ifndef PIC_FIELD_CHUNK
 #define PIC_FIELD_CHUNK 64
 #endif
@@ -871,13 +877,24 @@ __device__ __forceinline__ double envelope(double t, double tr, double tf, doubl
   return 0.0;
 }
 
-template <typename R>
-__device__ __forceinline__ void field_chunk(const FieldArgs<R>& p, int chunk) {
-  constexpr int CH = kFieldChunk;
-  __shared__ R sEy[CH + 3], sEz[CH + 3];      // E^n, nodes i0-2 .. i0+CH
-  __shared__ R sBy[CH + 2], sBz[CH + 2];      // B, half-nodes i0-1 .. i0+CH
-  __shared__ R sJy[CH + 1], sJz[CH + 1];      // J, nodes i0-1 .. i0+CH-1
-  __shared__ R nEy[CH + 1], nEz[CH + 1];      // E^{n+1}, nodes i0-1 .. i0+CH-1
+// LDS elements of a field chunk of CH nodes
+template <int CH>
+constexpr int field_lds_elems() { return 8 * CH + 14; }
+
+// One chunk of CH nodes (the work-group has CH threads).  `ahead` is the
+// number of steps the run is past its device step counter (a launch that
+// advances several steps before the counter moves); `sm` holds
+// field_lds_elems<CH>() elements of LDS.
+template <typename R, int CH>
+__device__ __forceinline__ void field_chunk(const FieldArgs<R>& p, int chunk, int ahead, R* sm) {
+  R* sEy = sm;                    // E^n, nodes i0-2 .. i0+CH
+  R* sEz = sEy + (CH + 3);
+  R* sBy = sEz + (CH + 3);        // B, half-nodes i0-1 .. i0+CH
+  R* sBz = sBy + (CH + 2);
+  R* sJy = sBz + (CH + 2);        // J, nodes i0-1 .. i0+CH-1
+  R* sJz = sJy + (CH + 1);
+  R* nEy = sJz + (CH + 1);        // E^{n+1}, nodes i0-1 .. i0+CH-1
+  R* nEz = nEy + (CH + 1);
   const int t = threadIdx.x;
   const int i0 = chunk * CH;
   const int n = p.nx;
@@ -894,7 +911,7 @@ __device__ __forceinline__ void field_chunk(const FieldArgs<R>& p, int chunk) {
   // incident wave at t_{n+1/2} (work-group 0 only)
   double ey_in = 0.0, ez_in = 0.0;
   if (t == 0 && i0 == 0) {
-    const double th = ((double)*p.step + 0.5) * p.dtd;
+    const double th = ((double)(*p.step + ahead) + 0.5) * p.dtd;
     const double f = envelope(th, p.tr, p.tf, p.tl);
     ey_in = p.ay * f * sin(th);
     ez_in = p.az * f * cos(th);
@@ -1010,7 +1027,8 @@ __device__ __forceinline__ void field_chunk(const FieldArgs<R>& p, int chunk) {
 
 template <typename R>
 __global__ __launch_bounds__(kFieldChunk) void k_field(FieldArgs<R> p) {
-  field_chunk<R>(p, (int)blockIdx.x);
+  __shared__ R sm[field_lds_elems<kFieldChunk>()];
+  field_chunk<R, kFieldChunk>(p, (int)blockIdx.x, 0, sm);
 }
 
 // ---------------------------------------------------------------- sort
@@ -1458,18 +1476,22 @@ __global__ void k_check_rounding(unsigned first, unsigned count, unsigned long l
 template <typename R>
 struct SlotDev {
   PushArgs<R> push[2][2];   // [particle parity][field parity]
-  FieldArgs<R> field[2];    // [field parity]; tick = 0 (k_tick_batch advances)
+  FieldArgs<R> field[2];    // [field parity]; tick = 0 (the field pass advances the counter itself)
   SortArgs<R> sort[2];      // [source particle parity]
   int* cnt[2];
   int* cur[2];
   long long* count;         // [parity][species]
   long long* step;          // the run's device step counter
+  int* done;                // field chunks of the current step finished (zero between steps)
   long long target;         // the run stops once *step reaches target
   int sort_interval;
   int nx;
 };
 
 constexpr int kMaxSlots = 1024;
+// ints between two slots' done counters: one 128-byte line each, so that the
+// counting atomics of different runs do not queue on one line
+constexpr int kDoneStride = 32;
 
 // A value the whole wave shares, moved to scalar registers.
 __device__ __forceinline__ long long uniform(long long v) {
@@ -1528,10 +1550,14 @@ __global__ PIC_PUSH_BOUNDS void k_push_batch(const SlotDev<R>* __restrict__ slot
   push_one_tile<R, kBatchPPT, kBatchPPT>(S.push[pp][fp], tile, lds);
 }
 
+// The field pass also ends the step: the last of a run's chunks to finish
+// advances the run's step counter (every chunk of the run has read the
+// counter before it counts itself done).
 template <typename R>
 __global__ __launch_bounds__(kFieldChunk) void k_field_batch(const SlotDev<R>* __restrict__ slots,
                                                             const int* __restrict__ start, int n) {
   __shared__ int rng[kMaxSlots + 1];
+  __shared__ R sm[field_lds_elems<kFieldChunk>()];
   const SlotRanges sr = load_ranges(start, n, rng);
   const int b = (int)blockIdx.x;
   if (b >= sr.total()) return;
@@ -1539,7 +1565,17 @@ __global__ __launch_bounds__(kFieldChunk) void k_field_batch(const SlotDev<R>* _
   const SlotDev<R>& S = slots[sl];
   const long long st = uniform(*S.step);
   if (st >= S.target) return;
-  field_chunk<R>(S.field[st & 1], b - sr.first(sl));
+  field_chunk<R, kFieldChunk>(S.field[st & 1], b - sr.first(sl), 0, sm);
+  // relaxed: a block's read of the counter has returned (its value chose the
+  // buffers) before the block counts itself; acquire/release ordering here
+  // would write back and invalidate the L2 once per work-group
+  if (threadIdx.x == 0) {
+    const int chunks = sr.first(sl + 1) - sr.first(sl);
+    if (__hip_atomic_fetch_add(S.done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == chunks - 1) {
+      __hip_atomic_store(S.done, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      *S.step = st + 1;
+    }
+  }
 }
 
 template <typename R>
@@ -1588,12 +1624,117 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter_batch(const SlotD
   }
 }
 
+// ---------------------------------------------------------------- persistent batched steps
+// Grid-wide barrier for a launch whose work-groups are all resident at once
+// (the host sizes the grid from the kernel's occupancy).  Arrivals count in
+// kBarGroups group words and then in one top word, so that no word takes
+// more than about G / kBarGroups same-address atomics; the last arrival
+// bumps the generation word that the others poll.  A wait longer than
+// kBarTicks of the 100 MHz constant clock sets *err, and once *err is set
+// every wait ends at once: a launch always finishes, and the host reports
+// the error.  Words sit 128 bytes apart: [0] generation, [32] top,
+// [64 + 32 g] group g.
+constexpr int kBarGroups = 16;
+constexpr int kBarWords = 32 * (2 + kBarGroups);
+constexpr unsigned long long kBarTicks = 100000000ull;  // one second
+
+__device__ __forceinline__ void grid_sync(unsigned* w, int* err) {
+  // every wave's loads and stores complete, then one agent-scope release per
+  // work-group (an L2 write-back), relaxed counting and polling, and one
+  // acquire after the wait (polling with acquire loads would invalidate the
+  // caches on every poll, under the work-groups still running)
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned G = gridDim.x, g = blockIdx.x % kBarGroups;
+    const unsigned in_g = (G - 1 - g) / kBarGroups + 1;  // blocks b < G with b % kBarGroups == g
+    const unsigned groups = G < (unsigned)kBarGroups ? G : (unsigned)kBarGroups;
+    unsigned* gen = w;
+    const unsigned cur = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    bool last = false;
+    unsigned* gw = w + 64 + 32 * g;
+    // the last arrival of a group and the last overall pass the others'
+    // releases on (acquire, then release, through a fence each)
+    if (__hip_atomic_fetch_add(gw, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == in_g - 1) {
+      __hip_atomic_store(gw, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+      if (__hip_atomic_fetch_add(w + 32, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == groups - 1) {
+        __hip_atomic_store(w + 32, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+        __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        last = true;
+      }
+    }
+    if (!last) {
+      const unsigned long long t0 = wall_clock64();
+      while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == cur) {
+        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        if (wall_clock64() - t0 > kBarTicks) {
+          __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+}
+
+// Slots a persistent launch serves (its range tables live in LDS beside the
+// push window, and more of them would cost the push a work-group per CU).
+constexpr int kPersistSlots = 128;
+
+// `steps` batched steps in one launch: every work-group takes push tiles of
+// all resident runs in turn, then field chunks of kThreads nodes, with a
+// grid-wide barrier after each pass.  A run's step counter stays put during
+// the launch (every pass computes its step as counter + k) and advances once
+// at the end, by the number of steps the run had left, at most `steps`.
 template <typename R>
-__global__ void k_tick_batch(const SlotDev<R>* slots, int n) {
-  const int sl = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-  if (sl >= n) return;
-  long long* st = slots[sl].step;
-  if (*st < slots[sl].target) *st += 1;
+__global__ __launch_bounds__(kThreads, PIC_STEPS_MIN_WAVES) void k_steps_batch(const SlotDev<R>* __restrict__ slots,
+                                              const int* __restrict__ push_start,
+                                              const int* __restrict__ field_start, int n, int steps,
+                                              unsigned* bar, int* err) {
+  __shared__ unsigned long long lds[kLdsSlots];
+  __shared__ int rp[kPersistSlots + 1], rf[kPersistSlots + 1];
+  static_assert(field_lds_elems<kThreads>() * sizeof(double) <= sizeof(lds), "field chunk must fit the window");
+  for (int i = threadIdx.x; i <= n; i += blockDim.x) {
+    rp[i] = push_start[i];
+    rf[i] = field_start[i];
+  }
+  __syncthreads();
+  const SlotRanges P{rp, n}, F{rf, n};
+  const int G = (int)gridDim.x;
+  for (int k = 0; k < steps; ++k) {
+    for (int b = (int)blockIdx.x; b < P.total(); b += G) {
+      const int sl = P.slot(b);
+      const SlotDev<R>& S = slots[sl];
+      const long long st = uniform(*S.step) + k;
+      if (st >= S.target) continue;
+      const int pp = (int)((st / S.sort_interval) & 1), fp = (int)(st & 1);
+      __syncthreads();  // the block's previous tile is out of the window
+      push_one_tile<R, kBatchPPT, kBatchPPT>(S.push[pp][fp], b - P.first(sl), lds);
+    }
+    grid_sync(bar, err);
+    for (int b = (int)blockIdx.x; b < F.total(); b += G) {
+      const int sl = F.slot(b);
+      const SlotDev<R>& S = slots[sl];
+      const long long st = uniform(*S.step) + k;
+      if (st >= S.target) continue;
+      __syncthreads();
+      field_chunk<R, kThreads>(S.field[st & 1], b - F.first(sl), k, reinterpret_cast<R*>(lds));
+    }
+    grid_sync(bar, err);
+  }
+  // every work-group has read the counters before the last barrier
+  if (blockIdx.x == 0) {
+    for (int sl = threadIdx.x; sl < n; sl += blockDim.x) {
+      long long* p = slots[sl].step;
+      const long long v = *p, t = slots[sl].target;
+      if (v < t) *p = v + steps < t ? v + steps : t;
+    }
+  }
 }
 
 // ---------------------------------------------------------------- init

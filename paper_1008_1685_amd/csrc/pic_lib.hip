@@ -657,16 +657,23 @@ struct pic_batch {
   int cap[3];                 // work-group capacity: push, field, sort
   char* tab;                  // device slot table
   size_t slot_bytes;
-  int* start[3];              // device work ranges [max_slots + 1]
+  // device work ranges [max_slots + 1]: push tiles, field chunks, sort
+  // tiles, field chunks of the persistent launch (kThreads nodes)
+  int* start[4];
   long long* dummy_step;      // step counter of free slots
   long long* steps;           // [max_slots] gathered step counters
+  int* done;                  // [max_slots][kDoneStride] field chunks finished this step
+  unsigned* bar;              // grid barrier words of the persistent launch
+  int* err;                   // set by a persistent launch whose barrier timed out
   std::vector<pic_run*> runs;
   std::vector<long long> target;
-  std::vector<int> nblk[3];
+  std::vector<int> nblk[4];
+  bool persistent = false;    // steps of a quantum in one launch (else one launch per pass)
+  int persist_cap = 0;        // work-groups of the persistent launch that fit the device at once
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   // captured kernel nodes whose grid follows the resident work: kind 0 push,
-  // 1 field, 2 sort (hist and scatter)
+  // 1 field, 2 sort (hist and scatter), 3 persistent steps
   std::vector<std::pair<hipGraphNode_t, int>> nodes;
 };
 
@@ -675,22 +682,29 @@ namespace {
 size_t batch_layout(int prec, int max_slots, pic_batch* b, char* base) {
   Carver cv{base};
   char* tab = cv.take<char>(slot_bytes_for(prec) * max_slots);
-  int* st[3];
-  for (int k = 0; k < 3; ++k) st[k] = cv.take<int>(max_slots + 1);
+  int* st[4];
+  for (int k = 0; k < 4; ++k) st[k] = cv.take<int>(max_slots + 1);
   long long* dummy = cv.take<long long>(1);
   long long* steps = cv.take<long long>(max_slots);
+  int* done = cv.take<int>((size_t)kDoneStride * max_slots);
+  unsigned* bar = cv.take<unsigned>(kBarWords);
+  int* err = cv.take<int>(32);
   if (b) {
     b->tab = tab;
-    for (int k = 0; k < 3; ++k) b->start[k] = st[k];
+    for (int k = 0; k < 4; ++k) b->start[k] = st[k];
     b->dummy_step = dummy;
     b->steps = steps;
+    b->done = done;
+    b->bar = bar;
+    b->err = err;
   }
   return cv.off + 256;
 }
 
 template <typename R>
-SlotDev<R> make_slot(const pic_batch* b, const pic_run* r, long long target) {
+SlotDev<R> make_slot(const pic_batch* b, int slot, const pic_run* r, long long target) {
   SlotDev<R> e{};
+  e.done = b->done + (size_t)kDoneStride * slot;
   if (!r) {
     e.step = b->dummy_step;
     e.target = 0;
@@ -715,7 +729,7 @@ SlotDev<R> make_slot(const pic_batch* b, const pic_run* r, long long target) {
 
 template <typename R>
 pic_status write_slot(pic_batch* b, int slot, hipStream_t st) {
-  const SlotDev<R> e = make_slot<R>(b, b->runs[slot], b->target[slot]);
+  const SlotDev<R> e = make_slot<R>(b, slot, b->runs[slot], b->target[slot]);
   HIP_TRY(hipMemcpyAsync(b->tab + slot * b->slot_bytes, &e, sizeof(e), hipMemcpyHostToDevice, st));
   HIP_TRY(hipStreamSynchronize(st));
   return PIC_OK;
@@ -724,8 +738,8 @@ pic_status write_slot(pic_batch* b, int slot, hipStream_t st) {
 pic_status update_batch_grids(pic_batch* b);
 
 pic_status write_ranges(pic_batch* b, hipStream_t st) {
-  std::vector<int> h((size_t)3 * (b->max_slots + 1));
-  for (int k = 0; k < 3; ++k) {
+  std::vector<int> h((size_t)4 * (b->max_slots + 1));
+  for (int k = 0; k < 4; ++k) {
     int* o = h.data() + k * (b->max_slots + 1);
     o[0] = 0;
     for (int s = 0; s < b->max_slots; ++s) o[s + 1] = o[s] + b->nblk[k][s];
@@ -736,11 +750,13 @@ pic_status write_ranges(pic_batch* b, hipStream_t st) {
 }
 
 // Work-groups a run of n0 electrons, n1 ions and nx cells occupies in each
-// captured launch of a batch: push tiles, field chunks, sort tiles.
-void batch_need(long long n0, long long n1, int nx, int need[3]) {
+// captured launch of a batch: push tiles, field chunks, sort tiles, and the
+// field chunks of the persistent launch (no capacity: they follow nx).
+void batch_need(long long n0, long long n1, int nx, int need[4]) {
   need[0] = tiles_for(n0, kBatchTile) + tiles_for(n1, kBatchTile);
   need[1] = (nx + 3 + kFieldChunk - 1) / kFieldChunk;
   need[2] = sort_blocks_for(n0) + sort_blocks_for(n1);
+  need[3] = (nx + 3 + kThreads - 1) / kThreads;
 }
 
 // The resident runs leave room for `need`.
@@ -766,6 +782,13 @@ pic_status capture_batch(pic_batch* b, hipStream_t st) {
   int dev = 0, cus = 0;
   HIP_TRY(hipGetDevice(&dev));
   HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  if (b->persistent) {
+    int per_cu = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_steps_batch<R>, kThreads, 0));
+    if (per_cu < 1) return fail(PIC_EHIP, "persistent batch kernel does not fit a compute unit");
+    if (PIC_STEPS_BLOCKS_PER_CU > 0) per_cu = std::min(per_cu, PIC_STEPS_BLOCKS_PER_CU);
+    b->persist_cap = per_cu * cus;
+  }
   HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
   // every admitted run is at a multiple of the quantum here, so the sort
   // (when due) is the first stage of the quantum; grids are set to the
@@ -773,10 +796,14 @@ pic_status capture_batch(pic_batch* b, hipStream_t st) {
   hipLaunchKernelGGL(k_sort_hist_batch<R>, dim3(1), dim3(kSortThreads), 0, st, tab, b->start[2], n);
   hipLaunchKernelGGL(k_sort_scan_batch<R>, dim3(std::min(2 * n, cus)), dim3(1024), 0, st, tab, n);
   hipLaunchKernelGGL(k_sort_scatter_batch<R>, dim3(1), dim3(kSortThreads), 0, st, tab, b->start[2], n);
-  for (int q = 0; q < b->quantum; ++q) {
-    hipLaunchKernelGGL(k_push_batch<R>, dim3(1), dim3(kThreads), 0, st, tab, b->start[0], n);
-    hipLaunchKernelGGL(k_field_batch<R>, dim3(1), dim3(kFieldChunk), 0, st, tab, b->start[1], n);
-    hipLaunchKernelGGL(k_tick_batch<R>, dim3((n + 255) / 256), dim3(256), 0, st, tab, n);
+  if (b->persistent) {
+    hipLaunchKernelGGL(k_steps_batch<R>, dim3(1), dim3(kThreads), 0, st, tab, b->start[0], b->start[3], n,
+                       b->quantum, b->bar, b->err);
+  } else {
+    for (int q = 0; q < b->quantum; ++q) {
+      hipLaunchKernelGGL(k_push_batch<R>, dim3(1), dim3(kThreads), 0, st, tab, b->start[0], n);
+      hipLaunchKernelGGL(k_field_batch<R>, dim3(1), dim3(kFieldChunk), 0, st, tab, b->start[1], n);
+    }
   }
   hipError_t e = hipStreamEndCapture(st, &b->graph);
   if (e != hipSuccess) return fail(PIC_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
@@ -790,6 +817,7 @@ pic_status capture_batch(pic_batch* b, hipStream_t st) {
   const void* ffield = reinterpret_cast<const void*>(&k_field_batch<R>);
   const void* fhist = reinterpret_cast<const void*>(&k_sort_hist_batch<R>);
   const void* fscat = reinterpret_cast<const void*>(&k_sort_scatter_batch<R>);
+  const void* fsteps = reinterpret_cast<const void*>(&k_steps_batch<R>);
   b->nodes.clear();
   for (hipGraphNode_t nd : all) {
     hipGraphNodeType ty;
@@ -797,7 +825,8 @@ pic_status capture_batch(pic_batch* b, hipStream_t st) {
     if (ty != hipGraphNodeTypeKernel) continue;
     hipKernelNodeParams kp{};
     HIP_TRY(hipGraphKernelNodeGetParams(nd, &kp));
-    const int kind = kp.func == fpush ? 0 : kp.func == ffield ? 1 : (kp.func == fhist || kp.func == fscat) ? 2 : -1;
+    const int kind = kp.func == fpush ? 0 : kp.func == ffield ? 1 : (kp.func == fhist || kp.func == fscat) ? 2
+                     : kp.func == fsteps ? 3 : -1;
     if (kind >= 0) b->nodes.emplace_back(nd, kind);
   }
   return PIC_OK;
@@ -806,7 +835,10 @@ pic_status capture_batch(pic_batch* b, hipStream_t st) {
 // Set the grids of the captured launches to the resident work.
 pic_status update_batch_grids(pic_batch* b) {
   if (!b->exec) return PIC_OK;
-  const int work[3] = {batch_work(b, 0), batch_work(b, 1), batch_work(b, 2)};
+  // the persistent launch: enough work-groups for the larger pass, no more
+  // than fit the device at once (its barriers need every one resident)
+  const int work[4] = {batch_work(b, 0), batch_work(b, 1), batch_work(b, 2),
+                       std::min(b->persist_cap, std::max(batch_work(b, 0), batch_work(b, 3)))};
   for (auto& nk : b->nodes) {
     hipKernelNodeParams kp{};
     HIP_TRY(hipGraphKernelNodeGetParams(nk.first, &kp));
@@ -1418,7 +1450,7 @@ pic_status pic_batch_create(int32_t precision, int32_t max_slots, int32_t quantu
   b->cap[2] = (int)(max_particles / kSortTile) + 2 * max_slots;
   b->runs.assign(max_slots, nullptr);
   b->target.assign(max_slots, 0);
-  for (int k = 0; k < 3; ++k) b->nblk[k].assign(max_slots, 0);
+  for (int k = 0; k < 4; ++k) b->nblk[k].assign(max_slots, 0);
   hipStream_t st = S(stream);
   hipError_t e = hipMemsetAsync(d_ws, 0, need - 256, st);
   if (e != hipSuccess) {
@@ -1450,14 +1482,14 @@ pic_status pic_batch_admit(pic_batch* b, pic_run* r, int64_t n_steps, void* stre
       break;
     }
   if (free_slot < 0) return fail(PIC_EBUSY, "no free batch slot");
-  int need[3];
+  int need[4];
   batch_need(r->n_max[0], r->n_max[1], r->d.nx, need);
   for (int k = 0; k < 3; ++k)
     if (need[k] > b->cap[k]) return fail(PIC_EINVAL, "run exceeds the batch's work capacity");
   if (!batch_room(b, need)) return fail(PIC_EBUSY, "batch work capacity exhausted");
   b->runs[free_slot] = r;
   b->target[free_slot] = n_steps;
-  for (int k = 0; k < 3; ++k) b->nblk[k][free_slot] = need[k];
+  for (int k = 0; k < 4; ++k) b->nblk[k][free_slot] = need[k];
   hipStream_t st = S(stream);
   // batched steps use their own tile size: the push's tile ranges restart
   HIP_TRY(hipMemsetAsync(r->tpred, 0, 2 * sizeof(int), st));
@@ -1465,7 +1497,7 @@ pic_status pic_batch_admit(pic_batch* b, pic_run* r, int64_t n_steps, void* stre
   if (!ps) ps = write_ranges(b, st);
   if (ps) {
     b->runs[free_slot] = nullptr;
-    for (int k = 0; k < 3; ++k) b->nblk[k][free_slot] = 0;
+    for (int k = 0; k < 4; ++k) b->nblk[k][free_slot] = 0;
     return ps;
   }
   r->batch = b;
@@ -1480,7 +1512,7 @@ pic_status pic_batch_fits(const pic_batch* b, const pic_config* cfg, int32_t* no
   if (ps) return ps;
   if (d.prec != b->prec) return fail(PIC_EINVAL, "run precision differs from the batch");
   if (cfg->sort_interval != b->quantum) return fail(PIC_EINVAL, "run sort_interval must equal the batch quantum");
-  int need[3];
+  int need[4];
   batch_need(d.n_foil, d.n_foil, d.nx, need);
   *ever = 1;
   for (int k = 0; k < 3; ++k)
@@ -1511,9 +1543,27 @@ pic_status pic_batch_poll(pic_batch* b, int64_t* steps, void* stream) {
                      b->slot_bytes, off, b->max_slots, b->steps);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(steps, b->steps, b->max_slots * sizeof(long long), hipMemcpyDeviceToHost, st));
+  int err = 0;
+  HIP_TRY(hipMemcpyAsync(&err, b->err, sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   for (int s = 0; s < b->max_slots; ++s)
     if (!b->runs[s]) steps[s] = -1;
+  if (err) return fail(PIC_EHIP, "a persistent batch launch timed out in a grid barrier; its steps are not valid");
+  return PIC_OK;
+}
+
+pic_status pic_batch_set_persistent(pic_batch* b, int32_t on) {
+  if (!b || (on != 0 && on != 1)) return fail(PIC_EINVAL, "null batch or mode other than 0 / 1");
+  if (on && b->max_slots > kPersistSlots)
+    return fail(PIC_EINVAL, "persistent batch steps serve at most " + std::to_string(kPersistSlots) + " slots");
+  if ((bool)on == b->persistent) return PIC_OK;
+  b->persistent = on;
+  // captured again, in the new form, by the next pic_batch_step
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->nodes.clear();
   return PIC_OK;
 }
 
@@ -1531,7 +1581,7 @@ pic_status pic_batch_release(pic_batch* b, int32_t slot, void* stream) {
   HIP_TRY(hipMemsetAsync(r->tpred, 0, 2 * sizeof(int), st));  // single-run tiles from here
   b->runs[slot] = nullptr;
   b->target[slot] = 0;
-  for (int k = 0; k < 3; ++k) b->nblk[k][slot] = 0;
+  for (int k = 0; k < 4; ++k) b->nblk[k][slot] = 0;
   pic_status ps = b->prec == PIC_FP32 ? write_slot<float>(b, slot, st) : write_slot<double>(b, slot, st);
   if (!ps) ps = write_ranges(b, st);
   return ps;

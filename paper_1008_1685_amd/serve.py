@@ -62,6 +62,11 @@ class Batch:
     def step(self, n_quanta: int = 1):
         N.check(self.lib.pic_batch_step(self._h, int(n_quanta), self._st()), "pic_batch_step")
 
+    def set_persistent(self, on: bool):
+        """Launch each quantum's steps as one persistent launch (True) or as
+        one push and one field launch per step (False, the default)."""
+        N.check(self.lib.pic_batch_set_persistent(self._h, 1 if on else 0), "pic_batch_set_persistent")
+
     def poll(self) -> np.ndarray:
         N.check(self.lib.pic_batch_poll(self._h, self._steps, self._st()), "pic_batch_poll")
         return np.frombuffer(self._steps, dtype=np.int64).copy()
@@ -91,13 +96,15 @@ class Server:
 
     budget_bytes bounds the summed run workspaces resident at once;
     quanta_per_poll is how many captured quanta are enqueued between two
-    checks for finished runs."""
+    checks for finished runs; persistent selects the batch's launch form
+    (Batch.set_persistent)."""
 
     def __init__(self, budget_bytes: int, max_slots: int = 64, quantum: int = 16,
                  max_particles: int = 4 * 10 ** 7, max_cells: int = 2 * 10 ** 6,
-                 quanta_per_poll: int = 2, precision: str = "fp32"):
+                 quanta_per_poll: int = 2, precision: str = "fp32", persistent: bool = False):
         self.budget = int(budget_bytes)
         self.batch = Batch(precision, max_slots, quantum, max_particles, max_cells)
+        self.batch.set_persistent(persistent)
         self.quanta_per_poll = int(quanta_per_poll)
         self.peak_bytes = 0
 

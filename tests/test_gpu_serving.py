@@ -57,14 +57,16 @@ def _same(sa, da, sb, db):
         assert da[k] == pytest.approx(db[k], rel=1e-6, abs=1e-300), k
 
 
-def test_each_run_is_the_same_alone_and_in_the_mix():
+@pytest.mark.parametrize("persistent", [False, True], ids=["per-pass-launches", "persistent"])
+def test_each_run_is_the_same_alone_and_in_the_mix(persistent):
     from paper_1008_1685_amd.serve import Server
 
     cfgs = _req_cfgs()
     alone = [_alone(c) for c in cfgs]
     # staggered arrivals: runs join while others are already on the GPU
     reqs = [dict(arrival=0.002 * i, cfg=c) for i, c in enumerate(cfgs)]
-    srv = Server(budget_bytes=1 << 34, max_slots=4, max_particles=2 * 10 ** 6, max_cells=10 ** 5)
+    srv = Server(budget_bytes=1 << 34, max_slots=4, max_particles=2 * 10 ** 6, max_cells=10 ** 5,
+                 persistent=persistent)
     recs = srv.serve(reqs, keep_runs=True)
     assert len(recs) == 3
     by = {r["name"]: r for r in recs}
@@ -92,7 +94,8 @@ def test_budget_and_slot_reuse():
         assert r["latency"] >= r["done"] - r["admitted"] >= 0
 
 
-def test_every_run_of_a_request_stream_conserves_charge():
+@pytest.mark.parametrize("persistent", [False, True], ids=["per-pass-launches", "persistent"])
+def test_every_run_of_a_request_stream_conserves_charge(persistent):
     # many uneven runs sharing the batch through admission, sorts and slot
     # reuse: each run's integer Gauss law must hold exactly at the end
     from paper_1008_1685_amd.serve import Server
@@ -103,7 +106,7 @@ def test_every_run_of_a_request_stream_conserves_charge():
                 for r in reqs)
     max_c = max(round(r["cfg"]["box_lambda"] * r["cfg"]["cells_per_lambda"]) for r in reqs)
     srv = Server(budget_bytes=16 * 2 ** 30, max_slots=64, max_particles=64 * max_p,
-                 max_cells=64 * (max_c + 8))
+                 max_cells=64 * (max_c + 8), persistent=persistent)
     recs = srv.serve(reqs)
     assert len(recs) == len(reqs)
     bad = [(r["name"], r["diag"]["gauss_int"], r["diag"]["nonfinite"]) for r in recs
@@ -183,3 +186,13 @@ def test_a_non_finite_request_flags_only_itself():
         assert d["nonfinite"] == 0
         _same(*alone[k], run.get_state(), d)
     batch.close()
+
+
+def test_persistent_form_limits():
+    from paper_1008_1685_amd.serve import Batch
+
+    b = Batch(max_slots=129, quantum=16, max_particles=10 ** 5, max_cells=10 ** 4)
+    with pytest.raises(RuntimeError, match="at most 128 slots"):
+        b.set_persistent(True)
+    b.set_persistent(False)
+    b.close()

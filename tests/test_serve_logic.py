@@ -46,6 +46,9 @@ class FakeBatch:
                 return i
         raise AssertionError("admit called without a free slot")
 
+    def set_persistent(self, on):
+        self.persistent = on
+
     def step(self, n):
         for r in self.slots:
             if r is not None:
