@@ -412,31 +412,32 @@ def stress_bench(serve_kwargs, t_start=8.5, window=200, chunk=8, max_grid=512):
 
 
 def write_traffic(fetch, write, cfetch, cwrite, out_path, kernel="k_push", workload="c3",
-                  match="k_push"):
+                  match="k_push", last=50):
     """A traffic record (profiles/traffic.json, profiles/traffic_d2.json) from
     rocprofv3 counter_collection.csv files: FETCH_SIZE and WRITE_SIZE of the
-    last 50 launches whose name contains `match` (c3: --steps 50 --warmup 3950
-    --no-side-runs --no-serve; d2: --only-2d --no-side-runs) and of a plain
-    1 GiB device copy (torch b.copy_(a), the calibration of bytes reported
-    per byte moved)."""
+    last `last` launches whose name contains `match` (c3: the 50 timed steps of
+    --steps 50 --warmup 0 --no-side-runs --no-serve; d2: the 400 timed steps of
+    --only-2d --no-side-runs) and of a plain 1 GiB device copy (torch
+    b.copy_(a), the calibration of bytes reported per byte moved)."""
     import csv
 
     import numpy as np
 
     def kib(path, name, last=50):
         rows = [r for r in csv.DictReader(open(path)) if name in r["Kernel_Name"]]
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
         return float(np.mean([float(r["Counter_Value"]) for r in rows][-last:])), len(rows)
 
     f_copy, _ = kib(cfetch, "copyBuffer")
     w_copy, _ = kib(cwrite, "copyBuffer")
     f_factor, w_factor = 2 ** 30 / (f_copy * 1024), 2 ** 30 / (w_copy * 1024)
-    f_push, nf = kib(fetch, match)
-    w_push, nw = kib(write, match)
+    f_push, nf = kib(fetch, match, last)
+    w_push, nw = kib(write, match, last)
     out = dict(workload=workload, kernel=kernel, kernel_sha256=kernel_hash(kernel),
                fetch_kib=f_push, write_kib=w_push, fetch_factor=f_factor, write_factor=w_factor,
                read_bytes=f_push * 1024 * f_factor, write_bytes=w_push * 1024 * w_factor,
                bytes_per_launch=f_push * 1024 * f_factor + w_push * 1024 * w_factor,
-               launches_averaged=min(50, nf, nw))
+               launches_averaged=min(last, nf, nw))
     json.dump(out, open(out_path, "w"), indent=1)
     print(json.dumps(out), flush=True)
 
@@ -478,7 +479,7 @@ def main():
             if path == os.path.join(ROOT, "profiles", "traffic.json"):
                 path = os.path.join(ROOT, "profiles", "traffic_d2.json")
             write_traffic(*args.write_traffic, path, kernel="k_push2", workload="d2",
-                          match="k_push2<float>")
+                          match="k_push2<float>", last=400)
         else:
             write_traffic(*args.write_traffic, args.traffic_json)
         return

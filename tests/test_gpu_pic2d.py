@@ -119,6 +119,8 @@ def _shuffle_within(p, block, seed):
     (40000, 9000, 2.0, "sorted", True),      # weights other than the reference weight
     (5000, 1500, 2 / 32, "sorted", False),   # 2 rows: every stencil wraps the period twice
     (5000, 1500, 3 / 32, "tiles", False),    # 3 rows: cell keys with unused row codes
+    (40000, 9000, 2.0, "dense", False),      # 4 columns, ~150 per cell: 32-bit LDS boxes
+    (40000, 9000, 2.0, "dense", True),       # the same with weights other than the reference
 ])
 def test_move_and_deposit_bit_exact_without_fields(n_e, n_i, box_y, order, mixed_w):
     # E = B = 0: the push leaves u unchanged, so cells, offsets and currents
@@ -127,8 +129,9 @@ def test_move_and_deposit_bit_exact_without_fields(n_e, n_i, box_y, order, mixed
     sim = _oracle(cfg)
     nx, ny = sim.nx, sim.ny
     ordered = order != "none"
-    pe = random_particles2d(10 + n_e, n_e, 2, nx - 2, ny, sim.w_ref, 1e-3, 1e3, ordered)
-    pi = random_particles2d(11 + n_e, n_i, 2, nx - 2, ny, sim.w_ref, 1e-3, 1e2, ordered)
+    x_hi = 6 if order == "dense" else nx - 2
+    pe = random_particles2d(10 + n_e, n_e, 2, x_hi, ny, sim.w_ref, 1e-3, 1e3, ordered)
+    pi = random_particles2d(11 + n_e, n_i, 2, x_hi, ny, sim.w_ref, 1e-3, 1e2, ordered)
     if order == "tiles":
         tile = _run(cfg).info["tile"]
         pe, pi = _shuffle_within(pe, tile, 1), _shuffle_within(pi, tile, 2)
