@@ -407,7 +407,9 @@ def stress_bench(serve_kwargs, t_start=8.5, window=200, chunk=8, max_grid=512):
                          f"80000 cells, fp32 + compensated RR, stepped from step {warm} "
                          f"({warm / 800:.2f} periods, in the laser-foil interaction)",
                 max_grid=max_grid, pushes_per_s_alone=alone,
-                pushes_per_s_with_serving=n * done[0] / el, steps_with_serving=done[0],
+                pushes_per_s_with_serving=n * done[0] / el,
+                share=n * done[0] / el / alone,  # the stress run's rate beside the requests / alone
+                steps_with_serving=done[0],
                 gauss_int=d["gauss_int"], serving_under_load=serving)
 
 
@@ -582,6 +584,12 @@ def main():
         line["cpu_baseline"] = cpu_baseline(cfg, res["state"])
     if not args.no_serve:
         line["serving"] = serve_bench()
+        # the same stream with each quantum's steps in one persistent launch
+        # (measured slower; the default keeps a push and a field launch per step)
+        per = serve_bench(persistent=True)
+        line["serving_persistent_form"] = {k: per[k] for k in ("p50_s", "p99_s", "mean_s", "wall_s",
+                                                               "pushes_per_s", "failed_checks",
+                                                               "launch_form")}
         if not args.no_stress:
             line["stress"] = stress_bench(dict(), max_grid=args.stress_grid)
     print(json.dumps(line), flush=True)
