@@ -399,6 +399,12 @@ pic_status pic_batch_step(pic_batch* b, int32_t n_quanta, void* stream);
  * are not valid; the batch stays in error).  Blocking. */
 pic_status pic_batch_poll(pic_batch* b, int64_t* steps, void* stream);
 
+/* Advance every resident run to its n_steps: poll, enqueue the graph
+ * replays the longest remainder needs, poll again.  *quanta (may be null)
+ * receives the number of replays enqueued.  Runs stay resident (release
+ * them to read their state).  Blocking. */
+pic_status pic_batch_drain(pic_batch* b, int64_t* quanta, void* stream);
+
 /* Choose how a quantum's steps are launched: on = 0 (default), one
  * push-deposit and one field launch per step, 2 x quantum launches after the
  * sort; on = 1, one persistent launch per quantum whose work-groups (as many

@@ -1552,6 +1552,31 @@ pic_status pic_batch_poll(pic_batch* b, int64_t* steps, void* stream) {
   return PIC_OK;
 }
 
+pic_status pic_batch_drain(pic_batch* b, int64_t* quanta, void* stream) {
+  if (!b || !stream) return fail(PIC_EINVAL, "null batch or stream");
+  std::vector<int64_t> steps(b->max_slots);
+  int64_t total = 0;
+  // every resident run advances in the same quanta, so one round of
+  // replays covers the longest remainder; the second poll confirms it
+  for (int round = 0; round < 2; ++round) {
+    pic_status ps = pic_batch_poll(b, steps.data(), stream);
+    if (ps) return ps;
+    long long left = 0;
+    for (int s = 0; s < b->max_slots; ++s)
+      if (b->runs[s]) left = std::max(left, b->target[s] - (long long)steps[s]);
+    if (left <= 0) {
+      if (quanta) *quanta = total;
+      return PIC_OK;
+    }
+    const long long nq = (left + b->quantum - 1) / b->quantum;
+    if (nq > INT32_MAX) return fail(PIC_EINVAL, "remaining steps exceed one drain");
+    ps = pic_batch_step(b, (int32_t)nq, stream);
+    if (ps) return ps;
+    total += nq;
+  }
+  return fail(PIC_EHIP, "batch runs did not reach their step targets");
+}
+
 pic_status pic_batch_set_persistent(pic_batch* b, int32_t on) {
   if (!b || (on != 0 && on != 1)) return fail(PIC_EINVAL, "null batch or mode other than 0 / 1");
   if (on && b->max_slots > kPersistSlots)

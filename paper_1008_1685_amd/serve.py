@@ -62,6 +62,13 @@ class Batch:
     def step(self, n_quanta: int = 1):
         N.check(self.lib.pic_batch_step(self._h, int(n_quanta), self._st()), "pic_batch_step")
 
+    def drain(self) -> int:
+        """Advance every resident run to its step target; returns the number
+        of quanta enqueued."""
+        q = C.c_int64(0)
+        N.check(self.lib.pic_batch_drain(self._h, C.byref(q), self._st()), "pic_batch_drain")
+        return q.value
+
     def set_persistent(self, on: bool):
         """Launch each quantum's steps as one persistent launch (True) or as
         one push and one field launch per step (False, the default)."""

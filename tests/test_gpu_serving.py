@@ -196,3 +196,28 @@ def test_persistent_form_limits():
         b.set_persistent(True)
     b.set_persistent(False)
     b.close()
+
+
+@pytest.mark.parametrize("persistent", [False, True], ids=["per-pass-launches", "persistent"])
+def test_drain_runs_every_resident_run_to_its_target(persistent):
+    from paper_1008_1685_amd import Run
+    from paper_1008_1685_amd.serve import Batch, run_steps
+
+    cfgs = _req_cfgs()[:2]
+    alone = [_alone(c) for c in cfgs]
+    b = Batch(max_slots=4, quantum=16, max_particles=2 * 10 ** 6, max_cells=10 ** 5)
+    b.set_persistent(persistent)
+    runs, slots = [], []
+    for c in cfgs:
+        r = Run(c, stream=b.stream)
+        runs.append(r)
+        slots.append(b.admit(r, run_steps(c)))
+    q = b.drain()
+    steps = b.poll()
+    assert q >= max(run_steps(c) for c in cfgs) // 16
+    for r, sl, c, (sa, da) in zip(runs, slots, cfgs, alone):
+        assert steps[sl] == run_steps(c)
+        b.release(sl)
+        _same(sa, da, r.get_state(), r.diag())
+    assert b.drain() == 0  # nothing resident
+    b.close()
