@@ -415,8 +415,10 @@ pic_status pic_batch_drain(pic_batch* b, int64_t* quanta, void* stream);
  * run's fields, integer currents and particles are bit-identical either way
  * (Section 2 leapfrog cycle: gather-push-deposit, then the field advance).
  * The persistent form needs max_slots <= 128 (PIC_EINVAL otherwise).  Takes
- * effect at the next pic_batch_step (the graph is captured again).
- * Host-only. */
+ * effect at the next pic_batch_step (the graph is captured again).  Call it
+ * while no replay of the batch is in flight (before the first
+ * pic_batch_step, or after pic_batch_poll / pic_batch_drain): the old graph
+ * is destroyed here.  Host-only. */
 pic_status pic_batch_set_persistent(pic_batch* b, int32_t on);
 
 /* Detach the run of `slot` (its state stays in its workspace; pic_diag and
