@@ -221,3 +221,21 @@ def test_drain_runs_every_resident_run_to_its_target(persistent):
         _same(sa, da, r.get_state(), r.diag())
     assert b.drain() == 0  # nothing resident
     b.close()
+
+
+@pytest.mark.parametrize("persistent", [False, True], ids=["per-pass-launches", "persistent"])
+def test_fp64_batch_runs_are_the_same_alone_and_in_the_mix(persistent):
+    # the plain FP64 path through both batch launch forms
+    from paper_1008_1685_amd.serve import Server
+
+    cfgs = [dict(c, precision="fp64") for c in _req_cfgs()]
+    alone = [_alone(c) for c in cfgs]
+    reqs = [dict(arrival=0.0, cfg=c) for c in cfgs]
+    srv = Server(budget_bytes=1 << 34, max_slots=4, max_particles=2 * 10 ** 6, max_cells=10 ** 5,
+                 precision="fp64", persistent=persistent)
+    recs = srv.serve(reqs, keep_runs=True)
+    by = {r["name"]: r for r in recs}
+    for (sa, da), c in zip(alone, cfgs):
+        r = by[c["name"]]
+        _same(sa, da, r["run"].get_state(), r["diag"])
+        assert r["diag"]["gauss_int"] == 0
