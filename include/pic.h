@@ -399,6 +399,19 @@ pic_status pic_batch_step(pic_batch* b, int32_t n_quanta, void* stream);
  * are not valid; the batch stays in error).  Blocking. */
 pic_status pic_batch_poll(pic_batch* b, int64_t* steps, void* stream);
 
+/* Queue a poll of every slot's step behind the replays already queued on
+ * `stream`, without waiting: the counters land in pinned host memory the
+ * batch owns.  One poll may be queued at a time (PIC_EINVAL otherwise).
+ * With pic_batch_poll_wait this keeps the device busy while the host reads
+ * the previous round's steps.  Async. */
+pic_status pic_batch_poll_async(pic_batch* b, void* stream);
+
+/* Wait for the queued poll and copy its steps to steps[max_slots]: -1 for
+ * slots free now or whose run was admitted or released after the poll was
+ * queued (their counters belong to another run).  PIC_EINVAL if no poll is
+ * queued; PIC_EHIP as pic_batch_poll.  Blocking (on the poll only). */
+pic_status pic_batch_poll_wait(pic_batch* b, int64_t* steps);
+
 /* Advance every resident run to its n_steps: poll, enqueue the graph
  * replays the longest remainder needs, poll again.  *quanta (may be null)
  * receives the number of replays enqueued.  Runs stay resident (release
@@ -414,6 +427,10 @@ pic_status pic_batch_drain(pic_batch* b, int64_t* quanta, void* stream);
  * Both forms execute the same per-particle and per-node arithmetic, so a
  * run's fields, integer currents and particles are bit-identical either way
  * (Section 2 leapfrog cycle: gather-push-deposit, then the field advance).
+ * on = 2 is the persistent form with every grid-barrier wait cut to zero:
+ * the launch still finishes but its barrier waits time out, its steps are
+ * not valid and the next poll returns PIC_EHIP (a test of that error path;
+ * the batch stays in error).
  * The persistent form needs max_slots <= 128 (PIC_EINVAL otherwise).  Takes
  * effect at the next pic_batch_step (the graph is captured again).  Call it
  * while no replay of the batch is in flight (before the first

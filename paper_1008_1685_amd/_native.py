@@ -292,6 +292,8 @@ SIGNATURES = {
     "pic_batch_release": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     "pic_batch_set_persistent": (C.c_int, [C.c_void_p, C.c_int32]),
     "pic_batch_drain": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.c_void_p]),
+    "pic_batch_poll_async": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "pic_batch_poll_wait": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     "pic_batch_free": (None, [C.c_void_p]),
     "pic2d_workspace_bytes": (C.c_int, [C.POINTER(Pic2dConfig), C.POINTER(C.c_size_t)]),
     "pic2d_init": (C.c_int, [C.POINTER(Pic2dConfig), C.c_void_p, C.c_size_t, C.c_void_p,

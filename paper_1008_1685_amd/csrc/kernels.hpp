@@ -1630,15 +1630,15 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter_batch(const SlotD
 // kBarGroups group words and then in one top word, so that no word takes
 // more than about G / kBarGroups same-address atomics; the last arrival
 // bumps the generation word that the others poll.  A wait longer than
-// kBarTicks of the 100 MHz constant clock sets *err, and once *err is set
-// every wait ends at once: a launch always finishes, and the host reports
-// the error.  Words sit 128 bytes apart: [0] generation, [32] top,
-// [64 + 32 g] group g.
+// `ticks` of the 100 MHz constant clock (one second in use) sets *err, and
+// once *err is set every wait ends at once: a launch always finishes, and
+// the host reports the error.  Words sit 128 bytes apart: [0] generation,
+// [32] top, [64 + 32 g] group g.
 constexpr int kBarGroups = 16;
 constexpr int kBarWords = 32 * (2 + kBarGroups);
 constexpr unsigned long long kBarTicks = 100000000ull;  // one second
 
-__device__ __forceinline__ void grid_sync(unsigned* w, int* err) {
+__device__ __forceinline__ void grid_sync(unsigned* w, int* err, unsigned long long ticks) {
   // every wave's loads and stores complete, then one agent-scope release per
   // work-group (an L2 write-back), relaxed counting and polling, and one
   // acquire after the wait (polling with acquire loads would invalidate the
@@ -1670,7 +1670,7 @@ __device__ __forceinline__ void grid_sync(unsigned* w, int* err) {
       const unsigned long long t0 = wall_clock64();
       while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == cur) {
         if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-        if (wall_clock64() - t0 > kBarTicks) {
+        if (wall_clock64() - t0 > ticks) {
           __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           break;
         }
@@ -1695,7 +1695,7 @@ template <typename R>
 __global__ __launch_bounds__(kThreads, PIC_STEPS_MIN_WAVES) void k_steps_batch(const SlotDev<R>* __restrict__ slots,
                                               const int* __restrict__ push_start,
                                               const int* __restrict__ field_start, int n, int steps,
-                                              unsigned* bar, int* err) {
+                                              unsigned* bar, int* err, unsigned long long ticks) {
   __shared__ unsigned long long lds[kLdsSlots];
   __shared__ int rp[kPersistSlots + 1], rf[kPersistSlots + 1];
   static_assert(field_lds_elems<kThreads>() * sizeof(double) <= sizeof(lds), "field chunk must fit the window");
@@ -1716,7 +1716,7 @@ __global__ __launch_bounds__(kThreads, PIC_STEPS_MIN_WAVES) void k_steps_batch(c
       __syncthreads();  // the block's previous tile is out of the window
       push_one_tile<R, kBatchPPT, kBatchPPT>(S.push[pp][fp], b - P.first(sl), lds);
     }
-    grid_sync(bar, err);
+    grid_sync(bar, err, ticks);
     for (int b = (int)blockIdx.x; b < F.total(); b += G) {
       const int sl = F.slot(b);
       const SlotDev<R>& S = slots[sl];
@@ -1725,7 +1725,7 @@ __global__ __launch_bounds__(kThreads, PIC_STEPS_MIN_WAVES) void k_steps_batch(c
       __syncthreads();
       field_chunk<R, kThreads>(S.field[st & 1], b - F.first(sl), k, reinterpret_cast<R*>(lds));
     }
-    grid_sync(bar, err);
+    grid_sync(bar, err, ticks);
   }
   // every work-group has read the counters before the last barrier
   if (blockIdx.x == 0) {

@@ -669,12 +669,20 @@ struct pic_batch {
   std::vector<long long> target;
   std::vector<int> nblk[4];
   bool persistent = false;    // steps of a quantum in one launch (else one launch per pass)
+  unsigned long long bar_ticks = kBarTicks;  // longest grid-barrier wait of the persistent launch
   int persist_cap = 0;        // work-groups of the persistent launch that fit the device at once
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   // captured kernel nodes whose grid follows the resident work: kind 0 push,
   // 1 field, 2 sort (hist and scatter), 3 persistent steps
   std::vector<std::pair<hipGraphNode_t, int>> nodes;
+  // asynchronous poll: step counters and the error word land in pinned host
+  // memory behind the queued replays; a slot whose run changed since the
+  // poll was queued (admit or release bump its generation) reads -1
+  long long* pin_steps = nullptr;  // [max_slots + 1], the last entry the error word
+  hipEvent_t poll_ev = nullptr;
+  bool poll_pending = false;
+  std::vector<unsigned long long> gen, gen_snap;
 };
 
 namespace {
@@ -798,7 +806,7 @@ pic_status capture_batch(pic_batch* b, hipStream_t st) {
   hipLaunchKernelGGL(k_sort_scatter_batch<R>, dim3(1), dim3(kSortThreads), 0, st, tab, b->start[2], n);
   if (b->persistent) {
     hipLaunchKernelGGL(k_steps_batch<R>, dim3(1), dim3(kThreads), 0, st, tab, b->start[0], b->start[3], n,
-                       b->quantum, b->bar, b->err);
+                       b->quantum, b->bar, b->err, b->bar_ticks);
   } else {
     for (int q = 0; q < b->quantum; ++q) {
       hipLaunchKernelGGL(k_push_batch<R>, dim3(1), dim3(kThreads), 0, st, tab, b->start[0], n);
@@ -1450,18 +1458,26 @@ pic_status pic_batch_create(int32_t precision, int32_t max_slots, int32_t quantu
   b->cap[2] = (int)(max_particles / kSortTile) + 2 * max_slots;
   b->runs.assign(max_slots, nullptr);
   b->target.assign(max_slots, 0);
+  b->gen.assign(max_slots, 0);
+  b->gen_snap.assign(max_slots, 0);
+  if (hipHostMalloc(reinterpret_cast<void**>(&b->pin_steps), (max_slots + 1) * sizeof(long long)) != hipSuccess ||
+      hipEventCreateWithFlags(&b->poll_ev, hipEventDisableTiming) != hipSuccess) {
+    if (b->pin_steps) (void)hipHostFree(b->pin_steps);
+    delete b;
+    return fail(PIC_EHIP, "batch poll buffer or event");
+  }
   for (int k = 0; k < 4; ++k) b->nblk[k].assign(max_slots, 0);
   hipStream_t st = S(stream);
   hipError_t e = hipMemsetAsync(d_ws, 0, need - 256, st);
   if (e != hipSuccess) {
-    delete b;
+    pic_batch_free(b);
     return fail(PIC_EHIP, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
   }
   for (int s = 0; s < max_slots && !ps; ++s)
     ps = precision == PIC_FP32 ? write_slot<float>(b, s, st) : write_slot<double>(b, s, st);
   if (!ps) ps = write_ranges(b, st);
   if (ps) {
-    delete b;
+    pic_batch_free(b);
     return ps;
   }
   *out = b;
@@ -1501,6 +1517,7 @@ pic_status pic_batch_admit(pic_batch* b, pic_run* r, int64_t n_steps, void* stre
     return ps;
   }
   r->batch = b;
+  ++b->gen[free_slot];
   *slot = free_slot;
   return PIC_OK;
 }
@@ -1552,6 +1569,36 @@ pic_status pic_batch_poll(pic_batch* b, int64_t* steps, void* stream) {
   return PIC_OK;
 }
 
+pic_status pic_batch_poll_async(pic_batch* b, void* stream) {
+  if (!b || !stream) return fail(PIC_EINVAL, "null batch or stream");
+  if (b->poll_pending) return fail(PIC_EINVAL, "a poll of this batch is already queued");
+  hipStream_t st = S(stream);
+  const size_t off = b->prec == PIC_FP32 ? offsetof(SlotDev<float>, step) : offsetof(SlotDev<double>, step);
+  hipLaunchKernelGGL(k_gather_steps, dim3((b->max_slots + 255) / 256), dim3(256), 0, st, b->tab,
+                     b->slot_bytes, off, b->max_slots, b->steps);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(b->pin_steps, b->steps, b->max_slots * sizeof(long long), hipMemcpyDeviceToHost, st));
+  b->pin_steps[b->max_slots] = 0;
+  HIP_TRY(hipMemcpyAsync(b->pin_steps + b->max_slots, b->err, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipEventRecord(b->poll_ev, st));
+  b->gen_snap = b->gen;
+  b->poll_pending = true;
+  return PIC_OK;
+}
+
+pic_status pic_batch_poll_wait(pic_batch* b, int64_t* steps) {
+  if (!b || !steps) return fail(PIC_EINVAL, "null batch or output");
+  if (!b->poll_pending) return fail(PIC_EINVAL, "no poll of this batch is queued");
+  b->poll_pending = false;
+  HIP_TRY(hipEventSynchronize(b->poll_ev));
+  for (int s = 0; s < b->max_slots; ++s)
+    steps[s] = (b->runs[s] && b->gen[s] == b->gen_snap[s]) ? b->pin_steps[s] : -1;
+  int err = 0;
+  std::memcpy(&err, b->pin_steps + b->max_slots, sizeof(int));
+  if (err) return fail(PIC_EHIP, "a persistent batch launch timed out in a grid barrier; its steps are not valid");
+  return PIC_OK;
+}
+
 pic_status pic_batch_drain(pic_batch* b, int64_t* quanta, void* stream) {
   if (!b || !stream) return fail(PIC_EINVAL, "null batch or stream");
   std::vector<int64_t> steps(b->max_slots);
@@ -1578,11 +1625,13 @@ pic_status pic_batch_drain(pic_batch* b, int64_t* quanta, void* stream) {
 }
 
 pic_status pic_batch_set_persistent(pic_batch* b, int32_t on) {
-  if (!b || (on != 0 && on != 1)) return fail(PIC_EINVAL, "null batch or mode other than 0 / 1");
+  if (!b || on < 0 || on > 2) return fail(PIC_EINVAL, "null batch or mode other than 0 / 1 / 2");
   if (on && b->max_slots > kPersistSlots)
     return fail(PIC_EINVAL, "persistent batch steps serve at most " + std::to_string(kPersistSlots) + " slots");
-  if ((bool)on == b->persistent) return PIC_OK;
-  b->persistent = on;
+  const unsigned long long ticks = on == 2 ? 0ull : kBarTicks;
+  if ((on != 0) == b->persistent && ticks == b->bar_ticks) return PIC_OK;
+  b->persistent = on != 0;
+  b->bar_ticks = ticks;
   // captured again, in the new form, by the next pic_batch_step
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
@@ -1605,6 +1654,7 @@ pic_status pic_batch_release(pic_batch* b, int32_t slot, void* stream) {
   r->batch = nullptr;
   HIP_TRY(hipMemsetAsync(r->tpred, 0, 2 * sizeof(int), st));  // single-run tiles from here
   b->runs[slot] = nullptr;
+  ++b->gen[slot];
   b->target[slot] = 0;
   for (int k = 0; k < 4; ++k) b->nblk[k][slot] = 0;
   pic_status ps = b->prec == PIC_FP32 ? write_slot<float>(b, slot, st) : write_slot<double>(b, slot, st);
@@ -1616,6 +1666,11 @@ void pic_batch_free(pic_batch* b) {
   if (!b) return;
   for (int s = 0; s < b->max_slots; ++s)
     if (b->runs[s]) b->runs[s]->batch = nullptr;
+  if (b->poll_ev) {
+    if (b->poll_pending) (void)hipEventSynchronize(b->poll_ev);  // the copy into pin_steps ends first
+    (void)hipEventDestroy(b->poll_ev);
+  }
+  if (b->pin_steps) (void)hipHostFree(b->pin_steps);
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   delete b;

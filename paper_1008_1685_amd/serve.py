@@ -69,13 +69,24 @@ class Batch:
         N.check(self.lib.pic_batch_drain(self._h, C.byref(q), self._st()), "pic_batch_drain")
         return q.value
 
-    def set_persistent(self, on: bool):
+    def set_persistent(self, on):
         """Launch each quantum's steps as one persistent launch (True) or as
-        one push and one field launch per step (False, the default)."""
-        N.check(self.lib.pic_batch_set_persistent(self._h, 1 if on else 0), "pic_batch_set_persistent")
+        one push and one field launch per step (False, the default); 2 is the
+        persistent form with its barrier waits cut to zero (the error path)."""
+        mode = on if isinstance(on, int) and not isinstance(on, bool) else (1 if on else 0)
+        N.check(self.lib.pic_batch_set_persistent(self._h, mode), "pic_batch_set_persistent")
 
     def poll(self) -> np.ndarray:
         N.check(self.lib.pic_batch_poll(self._h, self._steps, self._st()), "pic_batch_poll")
+        return np.frombuffer(self._steps, dtype=np.int64).copy()
+
+    def poll_async(self):
+        """Queue a poll of the step counters behind the queued replays."""
+        N.check(self.lib.pic_batch_poll_async(self._h, self._st()), "pic_batch_poll_async")
+
+    def poll_wait(self) -> np.ndarray:
+        """Steps of the queued poll (-1: free, or admitted or released since)."""
+        N.check(self.lib.pic_batch_poll_wait(self._h, self._steps), "pic_batch_poll_wait")
         return np.frombuffer(self._steps, dtype=np.int64).copy()
 
     def release(self, slot: int):
@@ -126,6 +137,7 @@ class Server:
         active = {}
         used = 0
         out = []
+        inflight = False  # a poll is queued behind the replays
         t0 = clock()
         while pending or queue or active:
             now = clock() - t0
@@ -152,13 +164,22 @@ class Server:
                 active[slot] = dict(req=req, run=run, steps=steps, need=need,
                                     admitted=clock() - t0)
             if not active:
+                if inflight:
+                    b.poll_wait()
+                    inflight = False
                 if pending:
                     time.sleep(max(0.0, pending[0]["arrival"] - (clock() - t0)))
                 continue
+            # the next round is queued before the host waits for the previous
+            # round's poll, so the device never idles on the round trip
             b.step(self.quanta_per_poll)
-            steps_now = b.poll()
+            steps_now = b.poll_wait() if inflight else None
+            b.poll_async()
+            inflight = True
+            if steps_now is None:
+                continue
             t_done = clock() - t0
-            for slot in [s for s, a in active.items() if steps_now[s] >= a["steps"]]:
+            for slot in [s for s, a in active.items() if 0 <= steps_now[s] and steps_now[s] >= a["steps"]]:
                 a = active.pop(slot)
                 b.release(slot)
                 d = a["run"].diag(allow_nonfinite=True)
@@ -172,4 +193,6 @@ class Server:
                     a["run"].close()
                 out.append(rec)
                 used -= a["need"]
+        if inflight:
+            b.poll_wait()
         return out

@@ -239,3 +239,56 @@ def test_fp64_batch_runs_are_the_same_alone_and_in_the_mix(persistent):
         r = by[c["name"]]
         _same(sa, da, r["run"].get_state(), r["diag"])
         assert r["diag"]["gauss_int"] == 0
+
+
+def test_async_poll_reports_only_runs_resident_when_it_was_queued():
+    from paper_1008_1685_amd import Run
+    from paper_1008_1685_amd._native import PicError
+    from paper_1008_1685_amd.serve import Batch, run_steps
+
+    cfgs = _req_cfgs()[:2]
+    b = Batch(max_slots=4, quantum=16, max_particles=2 * 10 ** 6, max_cells=10 ** 5)
+    ra = Run(cfgs[0], stream=b.stream)
+    sa = b.admit(ra, run_steps(cfgs[0]))
+    b.step(2)
+    b.poll_async()
+    with pytest.raises(PicError):
+        b.poll_async()  # one queued poll at a time
+    rb = Run(cfgs[1], stream=b.stream)
+    sb = b.admit(rb, run_steps(cfgs[1]))  # admitted after the poll was queued
+    steps = b.poll_wait()
+    assert steps[sa] == 32 and steps[sb] == -1
+    assert all(steps[s] == -1 for s in range(4) if s not in (sa, sb))
+    with pytest.raises(PicError):
+        b.poll_wait()  # nothing queued
+    b.step(1)
+    b.poll_async()
+    steps = b.poll_wait()
+    assert steps[sa] == 48 and steps[sb] == 16
+    b.release(sa)
+    b.release(sb)
+    b.close()
+
+
+def test_persistent_barrier_timeout_is_reported():
+    # every grid-barrier wait of the persistent launch cut to zero from the
+    # host (set_persistent(2)): the launch still ends (every wait is bounded)
+    # and the next poll reports the error instead of steps
+    from paper_1008_1685_amd import Run
+    from paper_1008_1685_amd._native import PicError
+    from paper_1008_1685_amd.serve import Batch, run_steps
+
+    cfgs = _req_cfgs()
+    b = Batch(max_slots=4, quantum=16, max_particles=2 * 10 ** 6, max_cells=10 ** 5)
+    b.set_persistent(2)
+    runs = []
+    for c in cfgs:
+        r = Run(c, stream=b.stream)
+        runs.append(r)
+        b.admit(r, run_steps(c))
+    b.step(1)
+    with pytest.raises(PicError, match="timed out"):
+        b.poll()
+    b.close()
+    for r in runs:
+        r.close()

@@ -57,6 +57,16 @@ class FakeBatch:
     def poll(self):
         return np.array([-1 if r is None else r.step for r in self.slots], np.int64)
 
+    def poll_async(self):
+        # the counters as queued behind the replays; a slot whose run changes
+        # before the wait reads -1, as the library reports it
+        self._snap = [(r, -1 if r is None else r.step) for r in self.slots]
+
+    def poll_wait(self):
+        out = [v if r is not None and r is self.slots[i] else -1 for i, (r, v) in enumerate(self._snap)]
+        self._snap = None
+        return np.array(out, np.int64)
+
     def release(self, slot):
         self.slots[slot] = None
 
