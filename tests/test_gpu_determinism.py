@@ -80,3 +80,44 @@ def test_1d_runs_repeat_bit_for_bit(name, precision, steps):
 def test_2d_runs_repeat_bit_for_bit(precision):
     cfg = preset2d("d1", precision=precision)
     assert _run2d(cfg, 384) == _run2d(cfg, 384)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_sort_interval_and_launch_split_leave_the_run_unchanged(precision):
+    # the integer currents, the fields and every particle (as a set, with its
+    # RR residuals) are independent of the particle order the sort leaves and
+    # of how a pass is split over launches: the same run with a sort every
+    # 8, 16 or 48 steps, and with its push and sort passes split into
+    # launches of 3 work-groups, ends in the same state
+    from paper_1008_1685_amd import Run
+
+    cfg = preset("c1", ppc=16, x_foil=2.0, box_lambda=6.0, pol="LP", a0=200.0, precision=precision)
+    steps = 1200  # the pulse reaches the foil after about 400 steps
+
+    def digest(interval, max_grid=0):
+        run = Run(dict(cfg, sort_interval=interval))
+        if max_grid:
+            run.set_max_grid(max_grid)
+        run.step(steps)
+        st = run.get_state()
+        keys = ["cell", "off", "ux", "uy", "uz", "w"] + [k for k in ("rx", "ry", "rz") if k in st["sp0"]]
+        h = hashlib.sha256()
+        for k in ("Ex_int", "Ey", "Ez", "By", "Bz", "Jx_int", "Jy_int", "Jz_int"):
+            h.update(np.ascontiguousarray(st[k]).tobytes())
+        for s in (0, 1):
+            p = st[f"sp{s}"]
+            alive = p["cell"] != np.iinfo(np.int32).min  # removed slots stay until the next sort
+            ks = [k for k in keys if k in p]
+            q = {k: p[k][alive] for k in ks}
+            order = np.lexsort([q[k] for k in reversed(ks)])
+            for k in ks:
+                h.update(np.ascontiguousarray(q[k][order]).tobytes())
+        d = run.diag()
+        run.close()
+        assert d["gauss_int"] == 0
+        return h.hexdigest()
+
+    ref = digest(16)
+    assert digest(8) == ref
+    assert digest(48) == ref
+    assert digest(16, max_grid=3) == ref
