@@ -183,6 +183,11 @@ typedef struct pic_state {
   pic_budget_state budget;   /* cumulative budget terms and the non-finite flag */
 } pic_state;
 
+/* The run handle: opaque, owned by the library (pic_init creates it,
+ * pic_free destroys it).  Declared here at file scope so that the
+ * prototypes below refer to one type in C as in C++. */
+struct pic_run;
+
 /* Workspace bytes a run with `cfg` needs (host-only; no GPU access). */
 pic_status pic_workspace_bytes(const pic_config* cfg, size_t* bytes);
 

@@ -140,6 +140,10 @@ typedef struct pic2d_state {
   pic_budget_state budget;   /* cumulative budget terms and the non-finite flag, as in pic.h */
 } pic2d_state;
 
+/* The 2D run handle: opaque, owned by the library (file-scope declaration,
+ * as for struct pic_run). */
+struct pic2d_run;
+
 /* Workspace bytes (host-only). */
 pic_status pic2d_workspace_bytes(const pic2d_config* cfg, size_t* bytes);
 

@@ -98,6 +98,7 @@ pic_status derive(const pic_config* c, Derived* d) {
   d->eps = 4.0 * M_PI / 3.0 * kRe_um / c->lambda_um;
   d->w_ref = c->n0 * d->dx / c->ppc;
   d->n_foil = (long long)d->nf * c->ppc;
+  if (c->capacity < 0) return fail(PIC_EINVAL, "capacity must be >= 0 (0: the foil's count)");
   d->cap = std::max<long long>(d->n_foil, c->capacity);
   // kernels address particle arrays with 32-bit byte offsets
   const long long elem = c->precision == PIC_FP32 ? 4 : 8;
@@ -932,9 +933,10 @@ const char* pic_last_error(void) { return g_err.c_str(); }
 pic_status pic_workspace_bytes(const pic_config* cfg, size_t* bytes) {
   if (!bytes) return fail(PIC_EINVAL, "null bytes pointer");
   pic_run tmp;
-  tmp.cfg = *cfg;
+  // validate (null config, struct_size of the caller's layout) before copying it
   pic_status st = derive(cfg, &tmp.d);
   if (st) return st;
+  tmp.cfg = *cfg;
   Carver cv{nullptr};
   carve(&tmp, cv);
   *bytes = cv.off + 256;
