@@ -3,10 +3,15 @@
  * every call here returns before any device work).  Prints one line per check
  * and "all host checks ran"; ASan aborts the process on a memory error. */
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include "pic.h"
 #include "pic2d.h"
+
+#ifdef WITH_GPU
+#include <hip/hip_runtime_api.h>
+#endif
 
 static int fails = 0;
 
@@ -69,7 +74,140 @@ static pic2d_config d1(void) {
   return c;
 }
 
-int main(void) {
+#ifdef WITH_GPU
+/* Device part: a small run and a batch, with every host buffer allocated at
+ * exactly the size the header documents, so that a write past it is caught. */
+static void* must(size_t bytes) {
+  void* p = calloc(1, bytes ? bytes : 1);
+  if (!p) {
+    printf("out of host memory\n");
+    exit(2);
+  }
+  return p;
+}
+
+static void gpu_checks(void) {
+  hipStream_t st;
+  if (hipStreamCreate(&st) != hipSuccess) {
+    printf("no HIP stream\n");
+    ++fails;
+    return;
+  }
+  pic_config c = c1();
+  c.ppc = 16;
+  c.box_lambda = 6.0;
+  c.x_foil = 2.0;
+  c.pol = PIC_LP;
+  size_t n = 0;
+  expect("gpu: workspace", pic_workspace_bytes(&c, &n), PIC_OK);
+  void* ws = NULL;
+  if (hipMalloc(&ws, n) != hipSuccess) {
+    printf("hipMalloc failed\n");
+    ++fails;
+    return;
+  }
+  struct pic_run* r = NULL;
+  expect("gpu: init", pic_init(&c, ws, n, st, &r), PIC_OK);
+  expect("gpu: step 200", pic_step(r, 200, st), PIC_OK);
+  pic_diag_out d;
+  memset(&d, 0, sizeof d);
+  expect("gpu: diag", pic_diag(r, &d, st), PIC_OK);
+  pic_info info;
+  memset(&info, 0, sizeof info);
+  expect("gpu: info", pic_get_info(r, &info), PIC_OK);
+  const long long cap = info.capacity, nc = info.n_cells;
+  pic_state s;
+  memset(&s, 0, sizeof s);
+  for (int k = 0; k < 2; ++k) {
+    s.sp[k].cell = (int32_t*)must(cap * sizeof(int32_t));
+    s.sp[k].off = must(cap * sizeof(float));
+    s.sp[k].ux = must(cap * sizeof(float));
+    s.sp[k].uy = must(cap * sizeof(float));
+    s.sp[k].uz = must(cap * sizeof(float));
+    s.sp[k].w = must(cap * sizeof(float));
+  }
+  s.sp[0].rx = (float*)must(cap * sizeof(float));
+  s.sp[0].ry = (float*)must(cap * sizeof(float));
+  s.sp[0].rz = (float*)must(cap * sizeof(float));
+  s.Ex = must((nc + 2) * sizeof(float));
+  s.Ey = must((nc + 1) * sizeof(float));
+  s.Ez = must((nc + 1) * sizeof(float));
+  s.By = must((nc + 2) * sizeof(float));
+  s.Bz = must((nc + 2) * sizeof(float));
+  s.Ex_int = (int64_t*)must((nc + 2) * sizeof(int64_t));
+  s.Jx_int = (int64_t*)must((nc + 2) * sizeof(int64_t));
+  s.Jy_int = (int64_t*)must((nc + 3) * sizeof(int64_t));
+  s.Jz_int = (int64_t*)must((nc + 3) * sizeof(int64_t));
+  expect("gpu: get_state", pic_get_state(r, &s, st), PIC_OK);
+  expect("gpu: set_state", pic_set_state(r, &s, st), PIC_OK);
+  expect("gpu: step 16", pic_step(r, 16, st), PIC_OK);
+  pic_species_state q;
+  memset(&q, 0, sizeof q);
+  q.cell = (int32_t*)must(100 * sizeof(int32_t));
+  q.off = must(100 * sizeof(float));
+  q.ux = must(100 * sizeof(float));
+  expect("gpu: get_particles 100", pic_get_particles(r, 0, 0, 100, &q, st), PIC_OK);
+  double* hist = (double*)must(64 * sizeof(double));
+  expect("gpu: spectrum 64 bins", pic_spectrum(r, 64, 100.0, hist, st), PIC_OK);
+  expect("gpu: spectrum, static 64 bins", pic_spectrum_static(r, 64, 100.0, hist, st), PIC_OK);
+
+  /* a batch of two runs */
+  size_t bw = 0;
+  expect("gpu: batch workspace", pic_batch_workspace_bytes(PIC_FP32, 3, &bw), PIC_OK);
+  void* bws = NULL;
+  if (hipMalloc(&bws, bw) != hipSuccess) {
+    ++fails;
+    return;
+  }
+  pic_batch* b = NULL;
+  expect("gpu: batch create", pic_batch_create(PIC_FP32, 3, 16, 1000000, 100000, bws, bw, st, &b), PIC_OK);
+  struct pic_run* br[2] = {NULL, NULL};
+  void* bwr[2] = {NULL, NULL};
+  int32_t slot[2] = {-1, -1};
+  for (int k = 0; k < 2; ++k) {
+    pic_config ck = c;
+    ck.seed = 7 + k;
+    ck.a0 = 150.0 + 50.0 * k;
+    if (hipMalloc(&bwr[k], n) != hipSuccess) {
+      ++fails;
+      return;
+    }
+    expect("gpu: batch run init", pic_init(&ck, bwr[k], n, st, &br[k]), PIC_OK);
+    expect("gpu: admit", pic_batch_admit(b, br[k], 96 + 32 * k, st, &slot[k]), PIC_OK);
+  }
+  int64_t* steps = (int64_t*)must(3 * sizeof(int64_t));
+  expect("gpu: batch step", pic_batch_step(b, 2, st), PIC_OK);
+  expect("gpu: batch poll", pic_batch_poll(b, steps, st), PIC_OK);
+  expect("gpu: batch poll queued", pic_batch_poll_async(b, st), PIC_OK);
+  expect("gpu: batch poll wait", pic_batch_poll_wait(b, steps), PIC_OK);
+  int64_t quanta = 0;
+  expect("gpu: batch drain", pic_batch_drain(b, &quanta, st), PIC_OK);
+  expect("gpu: batch persistent", pic_batch_set_persistent(b, 1), PIC_OK);
+  expect("gpu: batch release 0", pic_batch_release(b, slot[0], st), PIC_OK);
+  expect("gpu: batch release 1", pic_batch_release(b, slot[1], st), PIC_OK);
+  pic_batch_free(b);
+  for (int k = 0; k < 2; ++k) {
+    expect("gpu: released run diag", pic_diag(br[k], &d, st), PIC_OK);
+    pic_free(br[k]);
+    (void)hipFree(bwr[k]);
+  }
+  pic_free(r);
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(bws);
+  (void)hipFree(ws);
+  (void)hipStreamDestroy(st);
+  for (int k = 0; k < 2; ++k) {
+    free(s.sp[k].cell); free(s.sp[k].off); free(s.sp[k].ux); free(s.sp[k].uy); free(s.sp[k].uz);
+    free(s.sp[k].w);
+  }
+  free(s.sp[0].rx); free(s.sp[0].ry); free(s.sp[0].rz);
+  free(s.Ex); free(s.Ey); free(s.Ez); free(s.By); free(s.Bz);
+  free(s.Ex_int); free(s.Jx_int); free(s.Jy_int); free(s.Jz_int);
+  free(q.cell); free(q.off); free(q.ux); free(hist); free(steps);
+}
+#endif
+
+int main(int argc, char** argv) {
   size_t n = 0;
   pic_config c = c1();
   expect("1D workspace, c1", pic_workspace_bytes(&c, &n), PIC_OK);
@@ -124,6 +262,12 @@ int main(void) {
   expect("batch workspace, 100000 slots", pic_batch_workspace_bytes(PIC_FP32, 100000, &n), PIC_EINVAL);
   expect("batch workspace, bad precision", pic_batch_workspace_bytes(9, 4, &n), PIC_EINVAL);
   expect("rounding check without outputs", pic_check_rounding(0x3F800000u, 16, NULL, NULL), PIC_EINVAL);
+#ifdef WITH_GPU
+  if (argc > 1 && strcmp(argv[1], "--gpu") == 0) gpu_checks();
+#else
+  (void)argc;
+  (void)argv;
+#endif
   printf("all host checks ran: %d failed\n", fails);
   return fails ? 1 : 0;
 }

@@ -29,9 +29,12 @@ def test_host_code_is_clean_under_address_sanitizer(tmp_path):
     r = subprocess.run(build, capture_output=True, text=True, timeout=600)
     assert r.returncode == 0, r.stderr[-2000:]
     drv = tmp_path / "host_asan_driver"
-    link = [CLANG, "-Wall", "-Werror", "-fsanitize=address", "-fno-omit-frame-pointer", "-I", inc,
+    # with its device section compiled in (run with --gpu on a machine with a GPU)
+    link = [CLANG, "-Wall", "-Werror", "-DWITH_GPU", "-D__HIP_PLATFORM_AMD__", "-fsanitize=address",
+            "-fno-omit-frame-pointer", "-I", inc, "-I", "/opt/rocm/include",
             os.path.join(ROOT, "tests", "host_asan_driver.c"), "-L", str(tmp_path), "-lpic_asan",
-            f"-Wl,-rpath,{tmp_path}", "-o", str(drv)]
+            "-L", "/opt/rocm/lib", "-lamdhip64", f"-Wl,-rpath,{tmp_path}", "-Wl,-rpath,/opt/rocm/lib",
+            "-o", str(drv)]
     r = subprocess.run(link, capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stderr[-2000:]
     # leak checking is off: the HIP runtime's own start-up allocations are not ours
