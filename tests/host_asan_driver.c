@@ -151,6 +151,65 @@ static void gpu_checks(void) {
   expect("gpu: spectrum 64 bins", pic_spectrum(r, 64, 100.0, hist, st), PIC_OK);
   expect("gpu: spectrum, static 64 bins", pic_spectrum_static(r, 64, 100.0, hist, st), PIC_OK);
 
+  /* a 2D run: state I/O at the documented sizes */
+  {
+    pic2d_config c2 = d1();
+    size_t n2 = 0;
+    expect("gpu: 2D workspace", pic2d_workspace_bytes(&c2, &n2), PIC_OK);
+    void* ws2 = NULL;
+    if (hipMalloc(&ws2, n2) != hipSuccess) {
+      ++fails;
+      return;
+    }
+    struct pic2d_run* r2 = NULL;
+    expect("gpu: 2D init", pic2d_init(&c2, ws2, n2, st, &r2), PIC_OK);
+    expect("gpu: 2D step 64", pic2d_step(r2, 64, st), PIC_OK);
+    pic2d_info i2;
+    memset(&i2, 0, sizeof i2);
+    expect("gpu: 2D info", pic2d_get_info(r2, &i2), PIC_OK);
+    const long long cap2 = i2.capacity, nx = i2.nx, ny = i2.ny;
+    pic2d_state s2;
+    memset(&s2, 0, sizeof s2);
+    for (int k = 0; k < 2; ++k) {
+      s2.sp[k].cell = (int32_t*)must(cap2 * sizeof(int32_t));
+      s2.sp[k].ox = must(cap2 * sizeof(float));
+      s2.sp[k].oy = must(cap2 * sizeof(float));
+      s2.sp[k].ux = must(cap2 * sizeof(float));
+      s2.sp[k].uy = must(cap2 * sizeof(float));
+      s2.sp[k].uz = must(cap2 * sizeof(float));
+      s2.sp[k].w = must(cap2 * sizeof(float));
+    }
+    s2.sp[0].rx = (float*)must(cap2 * sizeof(float));
+    s2.sp[0].ry = (float*)must(cap2 * sizeof(float));
+    s2.sp[0].rz = (float*)must(cap2 * sizeof(float));
+    s2.Ex = must((nx + 2) * ny * sizeof(float));
+    s2.Ey = must((nx + 1) * ny * sizeof(float));
+    s2.Ez = must((nx + 1) * ny * sizeof(float));
+    s2.Bx = must((nx + 1) * ny * sizeof(float));
+    s2.By = must((nx + 2) * ny * sizeof(float));
+    s2.Bz = must((nx + 2) * ny * sizeof(float));
+    s2.Jx_int = (int64_t*)must((nx + 2) * ny * sizeof(int64_t));
+    s2.Jy_int = (int64_t*)must((nx + 3) * ny * sizeof(int64_t));
+    s2.Jz_int = (int64_t*)must((nx + 3) * ny * sizeof(int64_t));
+    s2.charge_int = (int64_t*)must((nx + 1) * ny * sizeof(int64_t));
+    expect("gpu: 2D get_state", pic2d_get_state(r2, &s2, st), PIC_OK);
+    expect("gpu: 2D set_state", pic2d_set_state(r2, &s2, st), PIC_OK);
+    expect("gpu: 2D step 8", pic2d_step(r2, 8, st), PIC_OK);
+    pic_diag_out d2;
+    memset(&d2, 0, sizeof d2);
+    expect("gpu: 2D diag", pic2d_diag(r2, &d2, st), PIC_OK);
+    pic2d_free(r2);
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(ws2);
+    for (int k = 0; k < 2; ++k) {
+      free(s2.sp[k].cell); free(s2.sp[k].ox); free(s2.sp[k].oy); free(s2.sp[k].ux);
+      free(s2.sp[k].uy); free(s2.sp[k].uz); free(s2.sp[k].w);
+    }
+    free(s2.sp[0].rx); free(s2.sp[0].ry); free(s2.sp[0].rz);
+    free(s2.Ex); free(s2.Ey); free(s2.Ez); free(s2.Bx); free(s2.By); free(s2.Bz);
+    free(s2.Jx_int); free(s2.Jy_int); free(s2.Jz_int); free(s2.charge_int);
+  }
+
   /* a batch of two runs */
   size_t bw = 0;
   expect("gpu: batch workspace", pic_batch_workspace_bytes(PIC_FP32, 3, &bw), PIC_OK);
