@@ -93,6 +93,13 @@ def window_start(cfg, warmup, t_start=T_START_PERIODS):
     return -(-lead // k) * k
 
 
+def sorts_in_window(start, steps, interval):
+    """Sorts that run inside steps [start, start + steps): one at the start of
+    every step that is a positive multiple of the sort interval."""
+    first = max(start, 1)
+    return max((start + steps - 1) // interval - (first - 1) // interval, 0)
+
+
 def time_run(cfg, steps, warmup, diag_every, timing=TIMING_PERIOD, t_start=T_START_PERIODS,
              keep_state=False, sort_cost=False):
     """Time `steps` steps of `cfg` after the lead-in to t_start periods plus
@@ -150,8 +157,7 @@ def time_run(cfg, steps, warmup, diag_every, timing=TIMING_PERIOD, t_start=T_STA
     d1 = run.diag()
     n_e = 0.5 * (d0["n_alive"][0] + d1["n_alive"][0])
     n_i = 0.5 * (d0["n_alive"][1] + d1["n_alive"][1])
-    # sort steps inside [start, start + steps)
-    sorts = (start + steps - 1) // interval - (start - 1) // interval
+    sorts = sorts_in_window(start, steps, interval)
     raw = t1 - t0
     seconds = raw if c_sort is None else raw - sorts * c_sort + steps / interval * c_sort
     out = dict(seconds=seconds, raw_seconds=raw, sorts_in_window=sorts, sort_cost_s=c_sort,

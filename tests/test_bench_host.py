@@ -36,6 +36,19 @@ def test_window_starts_in_the_interaction_at_a_sort_step():
     assert all(bench.window_start(cfg, w) % cfg["sort_interval"] == 0 for w in range(0, 200, 7))
 
 
+def test_sorts_in_the_window():
+    # the driver's 20 steps after the sort-cost half intervals: steps 4,064-4,083, no sort
+    assert bench.sorts_in_window(4064, 20, 64) == 0
+    assert bench.sorts_in_window(4032, 20, 64) == 1   # opens with the sort at 4,032
+    assert bench.sorts_in_window(4032, 256, 64) == 4
+    assert bench.sorts_in_window(1, 64, 64) == 1
+    assert bench.sorts_in_window(0, 64, 64) == 0      # step 0 has no sort
+    for start in range(0, 300, 13):
+        for steps in (1, 20, 64, 100):
+            brute = sum(1 for k in range(start, start + steps) if k > 0 and k % 64 == 0)
+            assert bench.sorts_in_window(start, steps, 64) == brute
+
+
 def _counter_file(path, name, counter, values):
     with open(path, "w", newline="") as f:
         w = csv.writer(f)
