@@ -142,3 +142,15 @@ def test_poisson_stream_shape():
     assert n.min() >= 0.9e4 and n.max() <= 1.1e6
     assert {r["cfg"]["pol"] for r in runs} == {"LP", "CP"}
     assert all(30 <= r["cfg"]["periods"] <= 80 for r in runs)
+
+
+def test_a_poll_queued_before_an_admission_does_not_release_the_new_run(fakes):
+    # one slot: the long run finishes (600 steps), the short one (200 steps)
+    # takes its slot while a poll queued before the admission still holds the
+    # long run's 600; the short run must be released only at its own target
+    srv = S.Server(budget_bytes=10 ** 9, max_slots=1)
+    reqs = _reqs(2, steps_periods=(3.0, 1.0))
+    recs = srv.serve(reqs)
+    assert [r["name"] for r in recs] == ["r0", "r1"]
+    for r in recs:
+        assert r["diag"]["step"] == r["steps"] == S.run_steps(reqs[int(r["name"][1:])]["cfg"])
