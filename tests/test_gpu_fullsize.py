@@ -59,6 +59,7 @@ def _sampled_push(cfg, run, fields, before, after, s, tol):
           f"{tol:.0e}); worst |du| / max(|u_oracle|, 1e-2) {err14.max():.2e}, within {tol:.0e} for "
           f"{100 * np.mean(err14 <= tol):.4f}%", flush=True)
     assert err <= tol, err
+    assert err14.max() <= tol, float(err14.max())
     # contract move from the stored momentum: bit-exact cell and offset
     c1, o1, *_ = contract.move(before["cell"][alive], before["off"][alive],
                                after["ux"][alive], after["uy"][alive], after["uz"][alive], cfg["cfl"])

@@ -161,14 +161,16 @@ def test_single_step_push_matches_oracle(precision, tol, rr):
         err = nrm(ug - un) / scale
         worst = max(worst, float(err.max()))
         # the single-step norm as first written for the oracle comparison,
-        # max(|u_oracle|, 1e-2): reported beside the scale used above, which
-        # adds |u_old|, |u_L|, |q dt E / m| and the RR increment (a step that
-        # nearly cancels a large momentum keeps the rounding of the large one)
+        # max(|u_oracle|, 1e-2), beside the scale used above, which adds
+        # |u_old|, |u_L|, |q dt E / m| and the RR increment (a step that
+        # nearly cancels a large momentum keeps the rounding of the large
+        # one).  On these inputs both hold (worst 4.9e-6 in FP32).
         err14 = nrm(ug - un) / np.maximum(nrm(un), 1e-2)
         c14 = float(np.mean(err14 <= tol))
         print(f"[{precision} rr={rr} species {s}] worst |du| / step scale {err.max():.2e} "
               f"(tolerance {tol:.0e}); worst |du| / max(|u_oracle|, 1e-2) {err14.max():.2e}, "
               f"within {tol:.0e} for {100 * c14:.3f}% of particles", flush=True)
+        assert err14.max() <= tol, (s, float(err14.max()))
         # positions: the oracle moves with its own momentum in FP64.  A
         # momentum error of tol * scale moves the particle by at most
         # cfl * tol * scale / gamma_new; add rounding of the stored offset
