@@ -566,11 +566,17 @@ def main():
         r_on = time_run(cfg, side, args.warmup, args.diag_every, timing=0)
         v_on = pushes_per_s(r_on, side)
         r_off = time_run(dict(cfg, rr=False), side, args.warmup, args.diag_every, timing=0)
+        r_nc = time_run(dict(cfg, rr_compensated=False), side, args.warmup, args.diag_every, timing=0)
         r_64 = time_run(dict(cfg, precision="fp64"), side, args.warmup, args.diag_every, timing=0)
         v_off = pushes_per_s(r_off, side)
+        v_nc = pushes_per_s(r_nc, side)
         v_64 = pushes_per_s(r_64, side)
+        # the RR arithmetic alone (no residual arrays: 44 B per push like RR
+        # off) and with the compensated accumulation (+24 B per electron)
         line["rr_cost"] = dict(pushes_per_s_rr_on=v_on, pushes_per_s_rr_off=v_off,
-                               overhead=v_off / v_on - 1.0, steps=side,
+                               overhead=v_off / v_on - 1.0,
+                               pushes_per_s_rr_on_uncompensated=v_nc,
+                               overhead_uncompensated=v_off / v_nc - 1.0, steps=side,
                                paper="about +10% compute time with RR (Section 3)")
         line["fp64_path"] = dict(pushes_per_s=v_64, pushes_per_s_fp32=v_on,
                                  speedup_fp32_over_fp64=v_on / v_64, steps=side)
