@@ -328,12 +328,19 @@ def cpu_baseline(cfg, state, budget_s=20.0, max_steps=12):
                        "where the timed window starts; numpy, one thread")
 
 
-def serve_bench(n_runs=256, rate=20.0, seed=0, max_slots=64, budget_gb=64.0, persistent=False):
+# batches the serving slots are split over (streams of their own); the
+# persistent form and the stress run's co-scheduling use one
+SERVE_GROUPS = 3
+
+
+def serve_bench(n_runs=256, rate=20.0, seed=0, max_slots=64, budget_gb=64.0, persistent=False,
+                groups=SERVE_GROUPS):
     """Serving form: a Poisson stream of independent laser-foil requests
     (a0, polarisation, density, thickness, size and length randomised),
     continuously batched; latency = completion - arrival.  persistent: each
     quantum's steps as one persistent launch rather than a push and a field
-    launch per step."""
+    launch per step; groups: the slots split over that many batches on
+    streams of their own."""
     import numpy as np
 
     from paper_1008_1685_amd.serve import Server, run_steps
@@ -345,7 +352,7 @@ def serve_bench(n_runs=256, rate=20.0, seed=0, max_slots=64, budget_gb=64.0, per
     max_c = max(round(r["cfg"]["box_lambda"] * r["cfg"]["cells_per_lambda"]) for r in reqs)
     srv = Server(budget_bytes=int(budget_gb * 2 ** 30), max_slots=max_slots,
                  max_particles=max_slots * max_p, max_cells=max_slots * (max_c + 8),
-                 persistent=persistent)
+                 persistent=persistent, groups=groups)
     t0 = time.perf_counter()
     recs = srv.serve(reqs)
     wall = time.perf_counter() - t0
@@ -357,7 +364,8 @@ def serve_bench(n_runs=256, rate=20.0, seed=0, max_slots=64, budget_gb=64.0, per
                 requests=len(recs), p50_s=float(np.percentile(lat, 50)),
                 p99_s=float(np.percentile(lat, 99)), mean_s=float(lat.mean()), wall_s=wall,
                 pushes=float(pushes), pushes_per_s=pushes / wall,
-                peak_resident_bytes=srv.peak_bytes, max_slots=max_slots, failed_checks=bad,
+                peak_resident_bytes=srv.peak_bytes, max_slots=max_slots, groups=len(srv.batches),
+                failed_checks=bad,
                 launch_form="one persistent launch per quantum" if persistent
                 else "a push and a field launch per step")
 
@@ -476,6 +484,8 @@ def main():
                     help="only run the serving measurement, on the first N requests")
     ap.add_argument("--serve-persistent", action="store_true",
                     help="with --serve-only: each quantum's steps as one persistent launch")
+    ap.add_argument("--serve-groups", type=int, default=SERVE_GROUPS, metavar="G",
+                    help="with --serve-only: the slots split over G batches on streams of their own")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
     ap.add_argument("--write-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
                                                          "COPY_WRITE_CSV"),
@@ -503,13 +513,15 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.serve_only:
         print(json.dumps(dict(serving=serve_bench(n_runs=args.serve_only,
-                                                  persistent=args.serve_persistent))), flush=True)
+                                                  persistent=args.serve_persistent,
+                                                  groups=args.serve_groups))), flush=True)
         return
     if args.only_2d:
         print(json.dumps(dict(pic2d=bench_2d(side_runs=not args.no_side_runs))), flush=True)
         return
     if args.stress_only:
-        print(json.dumps(dict(stress=stress_bench(dict(n_runs=args.stress_only), max_grid=args.stress_grid))),
+        print(json.dumps(dict(stress=stress_bench(dict(n_runs=args.stress_only, groups=1),
+                                                     max_grid=args.stress_grid))),
               flush=True)
         return
     cfg = preset(args.workload)
@@ -600,12 +612,12 @@ def main():
         line["serving"] = serve_bench()
         # the same stream with each quantum's steps in one persistent launch
         # (measured slower; the default keeps a push and a field launch per step)
-        per = serve_bench(persistent=True)
+        per = serve_bench(persistent=True, groups=1)
         line["serving_persistent_form"] = {k: per[k] for k in ("p50_s", "p99_s", "mean_s", "wall_s",
                                                                "pushes_per_s", "failed_checks",
                                                                "launch_form")}
         if not args.no_stress:
-            line["stress"] = stress_bench(dict(), max_grid=args.stress_grid)
+            line["stress"] = stress_bench(dict(groups=1), max_grid=args.stress_grid)
     print(json.dumps(line), flush=True)
 
 

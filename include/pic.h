@@ -436,6 +436,11 @@ pic_status pic_batch_drain(pic_batch* b, int64_t* quanta, void* stream);
  * the launch still finishes but its barrier waits time out, its steps are
  * not valid and the next poll returns PIC_EHIP (a test of that error path;
  * the batch stays in error).
+ * The persistent launch's work-groups wait for each other at the barriers,
+ * so they must all be resident at once: keep other launches (another
+ * batch's included) off the device while its replays run.  A barrier wait
+ * longer than about a second ends the launch and the next poll returns
+ * PIC_EHIP, as above.
  * The persistent form needs max_slots <= 128 (PIC_EINVAL otherwise).  Takes
  * effect at the next pic_batch_step (the graph is captured again).  Call it
  * while no replay of the batch is in flight (before the first

@@ -52,6 +52,12 @@ constexpr int kTile = kThreads * kPPT;
 // step of one run (the window set-up and flush are paid over fewer pushes).
 constexpr int kBatchPPT = PIC_BATCH_PPT;
 constexpr int kBatchTile = kThreads * kBatchPPT;
+#ifndef PIC_BATCH_DEPTH
+#define PIC_BATCH_DEPTH 2
+#endif
+// The batched push keeps two particles' loads in flight per thread rather
+// than the whole tile's: fewer registers, six waves per SIMD instead of five.
+constexpr int kBatchDepth = PIC_BATCH_DEPTH;
 constexpr int kMinTile = kTile < kBatchTile ? kTile : kBatchTile;
 constexpr int kLdsSlots = PIC_PUSH_LDS_SLOTS;  // 64-bit LDS current accumulators per work-group
 constexpr int kDepth = PIC_PUSH_DEPTH;        // particles per thread whose loads are in flight
@@ -661,6 +667,9 @@ template <typename R, bool RR, bool COMP, int PPT, int D>
 __device__ __forceinline__ void push_tile(const PushArgs<R>& a, int s, int tile, int n, int base,
                                           unsigned long long* lds) {
   static_assert(PPT % D == 0, "the load ring must divide the tile");
+  // the next particle's field loads are issued from its ring entry, which
+  // must be a different entry from the current particle's
+  static_assert(D >= 2 || PPT == 1, "a ring of one entry holds one particle per thread only");
   __shared__ int s_mn[kThreads / kLanes], s_mx[kThreads / kLanes];
   __shared__ double s_red[3][kThreads / kLanes];
   const SpeciesDev<R> sp = a.sp[s];
@@ -1547,7 +1556,7 @@ __global__ PIC_PUSH_BOUNDS void k_push_batch(const SlotDev<R>* __restrict__ slot
   const long long st = uniform(*S.step);
   if (st >= S.target) return;
   const int pp = (int)((st / S.sort_interval) & 1), fp = (int)(st & 1);
-  push_one_tile<R, kBatchPPT, kBatchPPT>(S.push[pp][fp], tile, lds);
+  push_one_tile<R, kBatchPPT, kBatchDepth>(S.push[pp][fp], tile, lds);
 }
 
 // The field pass also ends the step: the last of a run's chunks to finish
@@ -1714,7 +1723,7 @@ __global__ __launch_bounds__(kThreads, PIC_STEPS_MIN_WAVES) void k_steps_batch(c
       if (st >= S.target) continue;
       const int pp = (int)((st / S.sort_interval) & 1), fp = (int)(st & 1);
       __syncthreads();  // the block's previous tile is out of the window
-      push_one_tile<R, kBatchPPT, kBatchPPT>(S.push[pp][fp], b - P.first(sl), lds);
+      push_one_tile<R, kBatchPPT, kBatchDepth>(S.push[pp][fp], b - P.first(sl), lds);
     }
     grid_sync(bar, err, ticks);
     for (int b = (int)blockIdx.x; b < F.total(); b += G) {

@@ -110,34 +110,54 @@ def run_steps(cfg: dict) -> int:
 
 
 class Server:
-    """Continuous-batching request loop over one Batch.
+    """Continuous-batching request loop over one or more Batches.
 
     budget_bytes bounds the summed run workspaces resident at once;
     quanta_per_poll is how many captured quanta are enqueued between two
-    checks for finished runs; persistent selects the batch's launch form
-    (Batch.set_persistent)."""
+    checks for finished runs; persistent selects the batches' launch form
+    (Batch.set_persistent).  groups > 1 splits the max_slots slots over that
+    many batches, each on a stream of its own: their launches overlap on the
+    device, so one batch's short launches fill the ramp and tail of the
+    other's.  A request joins the group with the least resident work that
+    admits it.  The persistent form takes one group: its launch must have the
+    device to itself."""
 
     def __init__(self, budget_bytes: int, max_slots: int = 64, quantum: int = 16,
                  max_particles: int = 4 * 10 ** 7, max_cells: int = 2 * 10 ** 6,
-                 quanta_per_poll: int = 2, precision: str = "fp32", persistent: bool = False):
+                 quanta_per_poll: int = 2, precision: str = "fp32", persistent: bool = False,
+                 groups: int = 1):
         self.budget = int(budget_bytes)
-        self.batch = Batch(precision, max_slots, quantum, max_particles, max_cells)
-        self.batch.set_persistent(persistent)
+        if int(groups) < 1:
+            raise ValueError("groups must be >= 1")
+        if persistent and int(groups) > 1:
+            # its work-groups wait for each other at grid barriers, so they
+            # must all be resident at once, beside no other batch's launches
+            raise ValueError("the persistent form runs as one group")
+        groups = min(int(groups), int(max_slots))
+        per = [max_slots // groups + (1 if g < max_slots % groups else 0) for g in range(groups)]
+        self.batches = [Batch(precision, n, quantum, max_particles, max_cells) for n in per]
+        for b in self.batches:
+            b.set_persistent(persistent)
         self.quanta_per_poll = int(quanta_per_poll)
         self.peak_bytes = 0
+
+    @property
+    def batch(self):
+        return self.batches[0]
 
     def serve(self, requests, keep_runs: bool = False, clock=time.perf_counter):
         """requests: list of dict(arrival=seconds, cfg=...), sorted by arrival.
         Returns one record per request: arrival, admitted, done, latency
         (seconds, wall clock from the start of serve), steps, particles and
         final diagnostics (and the Run itself with keep_runs)."""
-        b = self.batch
+        G = len(self.batches)
         pending = collections.deque(sorted(requests, key=lambda r: r["arrival"]))
         queue = collections.deque()
-        active = {}
+        active = {}  # (group, slot) -> record
+        load = [0] * G  # resident workspace bytes per group
         used = 0
         out = []
-        inflight = False  # a poll is queued behind the replays
+        inflight = [False] * G  # a poll is queued behind the group's replays
         t0 = clock()
         while pending or queue or active:
             now = clock() - t0
@@ -148,40 +168,62 @@ class Server:
                 need = workspace_bytes(req["cfg"])
                 if used + need > self.budget and active:
                     break  # (a request larger than the whole budget runs alone)
-                fits_now, fits_ever = b.fits(req["cfg"])
-                if not fits_ever:
+                chosen, ever = None, False
+                for g in sorted(range(G), key=lambda g: load[g]):
+                    fits_now, fits_ever = self.batches[g].fits(req["cfg"])
+                    ever = ever or fits_ever
+                    if fits_now:
+                        chosen = g
+                        break
+                if not ever:
                     raise ValueError(f"request {req['cfg'].get('name', '')!r} exceeds the batch's "
                                      "work capacity (max_particles / max_cells)")
-                if not fits_now:
+                if chosen is None:
                     break
                 # the request is admitted: only now is its memory set aside
+                b = self.batches[chosen]
                 run = Run(req["cfg"], stream=b.stream)
                 steps = run_steps(req["cfg"])
                 slot = b.admit(run, steps)
                 queue.popleft()
                 used += need
+                load[chosen] += need
                 self.peak_bytes = max(self.peak_bytes, used)
-                active[slot] = dict(req=req, run=run, steps=steps, need=need,
-                                    admitted=clock() - t0)
+                active[(chosen, slot)] = dict(req=req, run=run, steps=steps, need=need,
+                                              admitted=clock() - t0)
             if not active:
-                if inflight:
-                    b.poll_wait()
-                    inflight = False
+                for g in range(G):
+                    if inflight[g]:
+                        self.batches[g].poll_wait()
+                        inflight[g] = False
                 if pending:
                     time.sleep(max(0.0, pending[0]["arrival"] - (clock() - t0)))
                 continue
-            # the next round is queued before the host waits for the previous
-            # round's poll, so the device never idles on the round trip
-            b.step(self.quanta_per_poll)
-            steps_now = b.poll_wait() if inflight else None
-            b.poll_async()
-            inflight = True
-            if steps_now is None:
+            busy = {g for g, _ in active}
+            # every busy group's next round is queued before the host waits
+            # for the previous round's polls, so the device never idles on
+            # the round trip
+            for g in sorted(busy):
+                self.batches[g].step(self.quanta_per_poll)
+            done = []
+            for g in range(G):
+                if not (inflight[g] or g in busy):
+                    continue
+                b = self.batches[g]
+                steps_now = b.poll_wait() if inflight[g] else None
+                inflight[g] = g in busy
+                if inflight[g]:
+                    b.poll_async()
+                if steps_now is not None:
+                    done += [(g, s) for (gg, s), a in active.items()
+                             if gg == g and 0 <= steps_now[s] and steps_now[s] >= a["steps"]]
+            if not done:
                 continue
             t_done = clock() - t0
-            for slot in [s for s, a in active.items() if 0 <= steps_now[s] and steps_now[s] >= a["steps"]]:
-                a = active.pop(slot)
-                b.release(slot)
+            for key in done:
+                g, slot = key
+                a = active.pop(key)
+                self.batches[g].release(slot)
                 d = a["run"].diag(allow_nonfinite=True)
                 rec = dict(name=a["req"]["cfg"].get("name", ""), arrival=a["req"]["arrival"],
                            admitted=a["admitted"], done=t_done,
@@ -193,6 +235,8 @@ class Server:
                     a["run"].close()
                 out.append(rec)
                 used -= a["need"]
-        if inflight:
-            b.poll_wait()
+                load[g] -= a["need"]
+        for g in range(G):
+            if inflight[g]:
+                self.batches[g].poll_wait()
         return out

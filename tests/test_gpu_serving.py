@@ -57,16 +57,18 @@ def _same(sa, da, sb, db):
         assert da[k] == pytest.approx(db[k], rel=1e-6, abs=1e-300), k
 
 
-@pytest.mark.parametrize("persistent", [False, True], ids=["per-pass-launches", "persistent"])
-def test_each_run_is_the_same_alone_and_in_the_mix(persistent):
+@pytest.mark.parametrize("persistent,groups", [(False, 1), (True, 1), (False, 2)],
+                         ids=["per-pass-launches", "persistent", "two-groups"])
+def test_each_run_is_the_same_alone_and_in_the_mix(persistent, groups):
     from paper_1008_1685_amd.serve import Server
 
     cfgs = _req_cfgs()
     alone = [_alone(c) for c in cfgs]
-    # staggered arrivals: runs join while others are already on the GPU
+    # staggered arrivals: runs join while others are already on the GPU; with
+    # two groups, two batches on streams of their own step at the same time
     reqs = [dict(arrival=0.002 * i, cfg=c) for i, c in enumerate(cfgs)]
     srv = Server(budget_bytes=1 << 34, max_slots=4, max_particles=2 * 10 ** 6, max_cells=10 ** 5,
-                 persistent=persistent)
+                 persistent=persistent, groups=groups)
     recs = srv.serve(reqs, keep_runs=True)
     assert len(recs) == 3
     by = {r["name"]: r for r in recs}
@@ -94,8 +96,9 @@ def test_budget_and_slot_reuse():
         assert r["latency"] >= r["done"] - r["admitted"] >= 0
 
 
-@pytest.mark.parametrize("persistent", [False, True], ids=["per-pass-launches", "persistent"])
-def test_every_run_of_a_request_stream_conserves_charge(persistent):
+@pytest.mark.parametrize("persistent,groups", [(False, 1), (True, 1), (False, 3)],
+                         ids=["per-pass-launches", "persistent", "three-groups"])
+def test_every_run_of_a_request_stream_conserves_charge(persistent, groups):
     # many uneven runs sharing the batch through admission, sorts and slot
     # reuse: each run's integer Gauss law must hold exactly at the end
     from paper_1008_1685_amd.serve import Server
@@ -106,7 +109,7 @@ def test_every_run_of_a_request_stream_conserves_charge(persistent):
                 for r in reqs)
     max_c = max(round(r["cfg"]["box_lambda"] * r["cfg"]["cells_per_lambda"]) for r in reqs)
     srv = Server(budget_bytes=16 * 2 ** 30, max_slots=64, max_particles=64 * max_p,
-                 max_cells=64 * (max_c + 8), persistent=persistent)
+                 max_cells=64 * (max_c + 8), persistent=persistent, groups=groups)
     recs = srv.serve(reqs)
     assert len(recs) == len(reqs)
     bad = [(r["name"], r["diag"]["gauss_int"], r["diag"]["nonfinite"]) for r in recs

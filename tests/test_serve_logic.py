@@ -154,3 +154,31 @@ def test_a_poll_queued_before_an_admission_does_not_release_the_new_run(fakes):
     assert [r["name"] for r in recs] == ["r0", "r1"]
     for r in recs:
         assert r["diag"]["step"] == r["steps"] == S.run_steps(reqs[int(r["name"][1:])]["cfg"])
+
+
+def test_groups_split_the_slots_and_share_the_requests(fakes):
+    srv = S.Server(budget_bytes=10 ** 9, max_slots=5, groups=2)
+    assert [b.max_slots for b in srv.batches] == [3, 2]
+    reqs = _reqs(7)
+    recs = srv.serve(reqs)
+    assert sorted(r["name"] for r in recs) == [f"r{i}" for i in range(7)]
+    for r in recs:
+        assert r["diag"]["step"] == r["steps"] == S.run_steps(reqs[int(r["name"][1:])]["cfg"])
+    assert all(b.admitted for b in srv.batches)
+    assert sorted(sum((b.admitted for b in srv.batches), [])) == sorted(r["name"] for r in recs)
+
+
+def test_a_request_joins_the_group_with_the_least_resident_work(fakes):
+    fakes.update(r0=400, r1=100, r2=100)
+    srv = S.Server(budget_bytes=10 ** 9, max_slots=4, groups=2)
+    srv.serve(_reqs(3))
+    # r0 (400) takes group 0; r1 and r2 go to group 1, which then holds 200
+    assert srv.batches[0].admitted == ["r0"] and srv.batches[1].admitted == ["r1", "r2"]
+
+
+def test_the_persistent_form_runs_as_one_group(fakes):
+    with pytest.raises(ValueError, match="one group"):
+        S.Server(budget_bytes=10 ** 9, max_slots=4, groups=2, persistent=True)
+    with pytest.raises(ValueError):
+        S.Server(budget_bytes=10 ** 9, max_slots=4, groups=0)
+    assert len(S.Server(budget_bytes=10 ** 9, max_slots=2, groups=3).batches) == 2
