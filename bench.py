@@ -267,6 +267,30 @@ def side_by_side_c2(warmup=3200, steps=2000):
     return out
 
 
+def copy_ceiling(nbytes=2 ** 31, reps=20):
+    """A STREAM-copy ceiling for the roofline: GB/s (bytes read + bytes
+    written) of a plain device-to-device copy of `nbytes`, timed with events
+    over `reps` copies after three untimed ones."""
+    import torch
+
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return dict(gbs=2 * nbytes / (ms * 1e-3) / 1e9,
+                what=f"device copy of {nbytes / 2 ** 30:g} GiB (torch copy_), read + written bytes "
+                     f"over the mean of {reps} copies")
+
+
 def small_runs():
     """Whole runs of the small workloads through pic_step (two sort intervals
     per graph replay): c1 (12,800 particles, 2,000 cells, 6,000 steps) and
@@ -572,6 +596,9 @@ def main():
         gauss_int=res["diag1"]["gauss_int"],
     )
     if not args.no_side_runs:
+        cc = copy_ceiling()
+        line["roofline"]["copy_ceiling"] = cc
+        line["roofline"]["frac_of_copy"] = achieved / cc["gbs"]
         # side runs over the same window (the same lead-in, at least 256 steps)
         # (a whole number of sort intervals: the sorts in the window are the configured share)
         side = max(-(-args.steps // cfg["sort_interval"]) * cfg["sort_interval"], 256)
