@@ -138,3 +138,12 @@ def test_2d_config_validation_on_host():
     assert lib.pic2d_diag(None, None, None) == N.PIC_EINVAL
     assert lib.pic2d_get_state(None, None, None) == N.PIC_EINVAL
     assert lib.pic2d_timing_enable(None, 1) == N.PIC_EINVAL
+
+
+def test_the_copy_ceiling_library_exports_its_entry_point():
+    # stream_copy (include/stream_copy.h): the measured copy ceiling of the
+    # roofline, built beside the main library
+    lib = C.CDLL(os.path.join(ROOT, "paper_1008_1685_amd", "libstreamcopy.so"))
+    assert hasattr(lib, "stream_copy")
+    txt = open(os.path.join(ROOT, "include", "stream_copy.h")).read()
+    assert "int stream_copy(const void* src, void* dst, size_t bytes, void* stream);" in txt
