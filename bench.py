@@ -380,19 +380,22 @@ SERVE_GROUPS = 3
 
 
 def serve_bench(n_runs=256, rate=20.0, seed=0, max_slots=64, budget_gb=64.0, persistent=False,
-                groups=SERVE_GROUPS):
+                groups=SERVE_GROUPS, saturated=False):
     """Serving form: a Poisson stream of independent laser-foil requests
     (a0, polarisation, density, thickness, size and length randomised),
     continuously batched; latency = completion - arrival.  persistent: each
     quantum's steps as one persistent launch rather than a push and a field
     launch per step; groups: the slots split over that many batches on
-    streams of their own."""
+    streams of their own; saturated: every request queued at time 0 (the
+    batch's throughput with no idle slot, rather than the stream's latency)."""
     import numpy as np
 
     from paper_1008_1685_amd.serve import Server, run_steps
     from workloads import poisson_stream
 
     reqs = poisson_stream(seed, n_runs=n_runs, rate=rate)
+    if saturated:
+        reqs = [dict(r, arrival=0.0) for r in reqs]
     max_p = max(2 * r["cfg"]["ppc"] * round(r["cfg"]["thickness"] * r["cfg"]["cells_per_lambda"])
                 for r in reqs)
     max_c = max(round(r["cfg"]["box_lambda"] * r["cfg"]["cells_per_lambda"]) for r in reqs)
@@ -404,12 +407,15 @@ def serve_bench(n_runs=256, rate=20.0, seed=0, max_slots=64, budget_gb=64.0, per
     wall = time.perf_counter() - t0
     lat = np.array([r["latency"] for r in recs])
     pushes = sum(r["particles"] * r["steps"] for r in recs)
+    # algorithmic bytes of those pushes (electrons and ions in equal numbers)
+    be, bi = alg_bytes_per_push("fp32", True, True)
     bad = sum(1 for r in recs if r["diag"]["gauss_int"] != 0 or r["diag"]["nonfinite"])
     return dict(workload=f"{n_runs} Poisson requests at {rate:g}/s (seed {seed}); a0 U[50,500], "
                          "LP/CP, n0 U[50,150], thickness U[0.5,2], 1e4-1e6 particles, 30-80 periods",
                 requests=len(recs), p50_s=float(np.percentile(lat, 50)),
                 p99_s=float(np.percentile(lat, 99)), mean_s=float(lat.mean()), wall_s=wall,
                 pushes=float(pushes), pushes_per_s=pushes / wall,
+                push_bytes_per_s_frac=pushes / wall * (be + bi) / 2 / (PEAK_HBM_GBS * 1e9),
                 peak_resident_bytes=srv.peak_bytes, max_slots=max_slots, groups=len(srv.batches),
                 failed_checks=bad,
                 launch_form="one persistent launch per quantum" if persistent
@@ -530,6 +536,8 @@ def main():
                     help="only run the serving measurement, on the first N requests")
     ap.add_argument("--serve-persistent", action="store_true",
                     help="with --serve-only: each quantum's steps as one persistent launch")
+    ap.add_argument("--serve-saturated", action="store_true",
+                    help="with --serve-only: every request queued at time 0")
     ap.add_argument("--serve-groups", type=int, default=SERVE_GROUPS, metavar="G",
                     help="with --serve-only: the slots split over G batches on streams of their own")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
@@ -560,7 +568,8 @@ def main():
     if args.serve_only:
         print(json.dumps(dict(serving=serve_bench(n_runs=args.serve_only,
                                                   persistent=args.serve_persistent,
-                                                  groups=args.serve_groups))), flush=True)
+                                                  groups=args.serve_groups,
+                                                  saturated=args.serve_saturated))), flush=True)
         return
     if args.only_2d:
         print(json.dumps(dict(pic2d=bench_2d(side_runs=not args.no_side_runs))), flush=True)
@@ -665,6 +674,14 @@ def main():
         line["serving_persistent_form"] = {k: per[k] for k in ("p50_s", "p99_s", "mean_s", "wall_s",
                                                                "pushes_per_s", "failed_checks",
                                                                "launch_form")}
+        # the same 256 requests all queued at time 0: the served batch's
+        # throughput when no slot idles (its whole pipeline: sorts, pushes,
+        # field passes and the host's admissions), as a fraction of the
+        # HBM peak by the pushes' algorithmic bytes
+        sat = serve_bench(saturated=True)
+        line["serving_saturated"] = {k: sat[k] for k in ("wall_s", "pushes", "pushes_per_s",
+                                                         "push_bytes_per_s_frac", "groups",
+                                                         "failed_checks", "p50_s", "p99_s")}
         if not args.no_stress:
             line["stress"] = stress_bench(dict(groups=1), max_grid=args.stress_grid)
     print(json.dumps(line), flush=True)
