@@ -277,7 +277,11 @@ def copy_ceiling(nbytes=2 ** 31, reps=20):
 
     import torch
 
-    lib = C.CDLL(os.path.join(ROOT, "paper_1008_1685_amd", "libstreamcopy.so"))
+    path = os.path.join(ROOT, "paper_1008_1685_amd", "libstreamcopy.so")
+    if not os.path.exists(path):  # a measurement aid: built here when missing
+        from paper_1008_1685_amd.build import build_stream_copy
+        build_stream_copy()
+    lib = C.CDLL(path)
     lib.stream_copy.restype = C.c_int
     lib.stream_copy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
     a = torch.arange(nbytes // 4, dtype=torch.int32, device="cuda")
