@@ -842,12 +842,12 @@ __global__ PIC_PUSH_BOUNDS void k_push(PushArgs<R> a) {
   push_one_tile<R, kPPT, kDepth>(a, a.tile0 + (int)blockIdx.x, lds);
 }
 
-// the same push in tiles of kBatchTile (the whole tile's loads up front),
-// for runs too small to fill the device with kTile tiles
+// the same push in tiles of kBatchTile (two particles' loads in flight, as
+// in the batched push), for runs too small to fill the device with kTile tiles
 template <typename R>
 __global__ PIC_PUSH_BOUNDS void k_push_small(PushArgs<R> a) {
   __shared__ unsigned long long lds[kLdsSlots];
-  push_one_tile<R, kBatchPPT, kBatchPPT>(a, a.tile0 + (int)blockIdx.x, lds);
+  push_one_tile<R, kBatchPPT, kBatchDepth>(a, a.tile0 + (int)blockIdx.x, lds);
 }
 
 // ---------------------------------------------------------------- fields
