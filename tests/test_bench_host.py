@@ -37,7 +37,7 @@ def test_window_starts_in_the_interaction_at_a_sort_step():
 
 
 def test_sorts_in_the_window():
-    # the driver's 20 steps after the sort-cost half intervals: steps 4,064-4,083, no sort
+    # 20 timed steps after the sort-cost half intervals: steps 4,064-4,083, no sort
     assert bench.sorts_in_window(4064, 20, 64) == 0
     assert bench.sorts_in_window(4032, 20, 64) == 1   # opens with the sort at 4,032
     assert bench.sorts_in_window(4032, 256, 64) == 4
