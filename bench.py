@@ -397,6 +397,8 @@ def serve_bench(n_runs=256, rate=20.0, seed=0, max_slots=64, budget_gb=64.0, per
     from paper_1008_1685_amd.serve import Server, run_steps
     from workloads import poisson_stream
 
+    if persistent:
+        groups = 1  # the persistent launch needs the device to itself
     reqs = poisson_stream(seed, n_runs=n_runs, rate=rate)
     if saturated:
         reqs = [dict(r, arrival=0.0) for r in reqs]
