@@ -89,3 +89,33 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stdout
+
+
+def test_serving_bench_passes_its_launch_form_and_groups(monkeypatch):
+    # serve_bench builds its Server with the requested groups, except that the
+    # persistent form always runs as one group; a saturated stream queues
+    # every request at time 0
+    import paper_1008_1685_amd.serve as S
+
+    made = []
+
+    class FakeServer:
+        def __init__(self, budget_bytes, max_slots, max_particles, max_cells, persistent, groups):
+            made.append(dict(persistent=persistent, groups=groups))
+            self.batches = [None] * groups
+            self.peak_bytes = 0
+
+        def serve(self, reqs):
+            made[-1]["arrivals"] = [r["arrival"] for r in reqs]
+            return [dict(latency=1.0, particles=10, steps=5, diag=dict(gauss_int=0, nonfinite=0))
+                    for _ in reqs]
+
+    monkeypatch.setattr(S, "Server", FakeServer)
+    r = bench.serve_bench(n_runs=4)
+    assert made[-1]["groups"] == bench.SERVE_GROUPS and not made[-1]["persistent"]
+    assert r["groups"] == bench.SERVE_GROUPS and r["pushes"] == 4 * 50
+    bench.serve_bench(n_runs=4, persistent=True)
+    assert made[-1]["groups"] == 1 and made[-1]["persistent"]
+    bench.serve_bench(n_runs=4, saturated=True, groups=2)
+    assert made[-1]["groups"] == 2 and made[-1]["arrivals"] == [0.0] * 4
+    assert max(made[0]["arrivals"]) > 0
