@@ -381,6 +381,8 @@ def cpu_baseline(cfg, state, budget_s=20.0, max_steps=12):
 # batches the serving slots are split over (streams of their own); the
 # persistent form and the stress run's co-scheduling use one
 SERVE_GROUPS = 3
+# steps per captured quantum of the serving batch: the requests' sort interval
+SERVE_QUANTUM = 32
 
 
 def serve_bench(n_runs=256, rate=20.0, seed=0, max_slots=64, budget_gb=64.0, persistent=False,
@@ -405,7 +407,7 @@ def serve_bench(n_runs=256, rate=20.0, seed=0, max_slots=64, budget_gb=64.0, per
     max_p = max(2 * r["cfg"]["ppc"] * round(r["cfg"]["thickness"] * r["cfg"]["cells_per_lambda"])
                 for r in reqs)
     max_c = max(round(r["cfg"]["box_lambda"] * r["cfg"]["cells_per_lambda"]) for r in reqs)
-    srv = Server(budget_bytes=int(budget_gb * 2 ** 30), max_slots=max_slots,
+    srv = Server(budget_bytes=int(budget_gb * 2 ** 30), max_slots=max_slots, quantum=SERVE_QUANTUM,
                  max_particles=max_slots * max_p, max_cells=max_slots * (max_c + 8),
                  persistent=persistent, groups=groups)
     t0 = time.perf_counter()

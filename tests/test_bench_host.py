@@ -93,20 +93,22 @@ def test_more_than_one_gpu_is_refused():
 
 def test_serving_bench_passes_its_launch_form_and_groups(monkeypatch):
     # serve_bench builds its Server with the requested groups, except that the
-    # persistent form always runs as one group; a saturated stream queues
-    # every request at time 0
+    # persistent form always runs as one group, and with the requests' sort
+    # interval as its quantum; a saturated stream queues every request at time 0
     import paper_1008_1685_amd.serve as S
 
     made = []
 
     class FakeServer:
-        def __init__(self, budget_bytes, max_slots, max_particles, max_cells, persistent, groups):
-            made.append(dict(persistent=persistent, groups=groups))
+        def __init__(self, budget_bytes, max_slots, quantum, max_particles, max_cells, persistent, groups):
+            made.append(dict(persistent=persistent, groups=groups, quantum=quantum))
             self.batches = [None] * groups
             self.peak_bytes = 0
 
         def serve(self, reqs):
             made[-1]["arrivals"] = [r["arrival"] for r in reqs]
+            # the batch takes runs whose sort interval is its quantum
+            assert all(r["cfg"]["sort_interval"] == made[-1]["quantum"] for r in reqs)
             return [dict(latency=1.0, particles=10, steps=5, diag=dict(gauss_int=0, nonfinite=0))
                     for _ in reqs]
 

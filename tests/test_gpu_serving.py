@@ -108,7 +108,8 @@ def test_every_run_of_a_request_stream_conserves_charge(persistent, groups):
     max_p = max(2 * r["cfg"]["ppc"] * round(r["cfg"]["thickness"] * r["cfg"]["cells_per_lambda"])
                 for r in reqs)
     max_c = max(round(r["cfg"]["box_lambda"] * r["cfg"]["cells_per_lambda"]) for r in reqs)
-    srv = Server(budget_bytes=16 * 2 ** 30, max_slots=64, max_particles=64 * max_p,
+    srv = Server(budget_bytes=16 * 2 ** 30, max_slots=64, quantum=reqs[0]["cfg"]["sort_interval"],
+                 max_particles=64 * max_p,
                  max_cells=64 * (max_c + 8), persistent=persistent, groups=groups)
     recs = srv.serve(reqs)
     assert len(recs) == len(reqs)

@@ -93,7 +93,7 @@ def poisson_stream(seed: int = 0, n_runs: int = 256, rate: float = 20.0,
                      n0=float(rng.uniform(50.0, 150.0)), x_foil=8.0,
                      thickness=foil_cells / cpl, ppc=ppc, mass_ratio=1836.0,
                      rr=True, rr_compensated=True, seed=i, jitter=0.5,
-                     periods=float(periods), sort_interval=16, name=f"req{i}")))
+                     periods=float(periods), sort_interval=32, name=f"req{i}")))
     return runs
 
 
