@@ -115,8 +115,9 @@ class Server:
     budget_bytes bounds the summed run workspaces resident at once; quantum
     is the steps of one captured replay, and every request's sort_interval
     must equal it (the sort opens each replay); quanta_per_poll is how many
-    captured quanta are enqueued between two checks for finished runs; persistent selects the batches' launch form
-    (Batch.set_persistent).  groups > 1 splits the max_slots slots over that
+    captured quanta are enqueued between two checks for finished runs;
+    persistent selects the batches' launch form (Batch.set_persistent).
+    groups > 1 splits the max_slots slots over that
     many batches, each on a stream of its own: their launches overlap on the
     device, so one batch's short launches fill the ramp and tail of the
     other's.  A request joins the group with the least resident work that
