@@ -118,23 +118,40 @@ def test_every_run_of_a_request_stream_conserves_charge(persistent, groups):
     assert not bad, bad
 
 
-def test_served_runs_match_the_oracle():
+_ORACLE_ROWS = {}
+
+
+def _oracle_rows(c):
+    # the oracle's diagnostics of a configuration over three seeds (computed
+    # once per configuration for every test that needs them)
+    from oracle import pic as opic
+    from paper_1008_1685_amd.serve import run_steps
+
+    if c["name"] not in _ORACLE_ROWS:
+        n = run_steps(c)
+        _ORACLE_ROWS[c["name"]] = [opic.Pic1D(dict(c, seed=c["seed"] + 100 * k)).run(n).diag()
+                                   for k in range(3)]
+    return _ORACLE_ROWS[c["name"]]
+
+
+@pytest.mark.parametrize("groups", [1, 3], ids=["one-group", "three-groups"])
+def test_served_runs_match_the_oracle(groups):
     # every served request against the FP64 oracle on its own configuration,
     # at the tolerances of the short runs: each energy term within 2e-3 of the
     # injected energy plus twice the oracle's own seed-to-seed spread (LP heats
-    # the electrons chaotically), the balance within 1e-3, alive counts exact
-    from oracle import pic as opic
-    from paper_1008_1685_amd.serve import Server, run_steps
+    # the electrons chaotically), the balance within 1e-3, alive counts exact;
+    # with three groups the requests step in batches on separate streams
+    from paper_1008_1685_amd.serve import Server
 
     keys = ("U_field", "K_e", "K_i", "E_rad", "E_out_left", "E_out_right", "E_esc")
     cfgs = _req_cfgs()
     reqs = [dict(arrival=0.002 * i, cfg=c) for i, c in enumerate(cfgs)]
-    srv = Server(budget_bytes=1 << 34, max_slots=4, max_particles=2 * 10 ** 6, max_cells=10 ** 5)
+    srv = Server(budget_bytes=1 << 34, max_slots=4, max_particles=2 * 10 ** 6, max_cells=10 ** 5,
+                 groups=groups)
     recs = {r["name"]: r for r in srv.serve(reqs)}
     for c in cfgs:
         d = recs[c["name"]]["diag"]
-        n = run_steps(c)
-        rows = [opic.Pic1D(dict(c, seed=c["seed"] + 100 * k)).run(n).diag() for k in range(3)]
+        rows = _oracle_rows(c)
         ref = rows[0]
         e_in = ref["E_in"]
         assert d["E_in"] == pytest.approx(e_in, rel=1e-6)
