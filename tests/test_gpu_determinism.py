@@ -121,3 +121,64 @@ def test_sort_interval_and_launch_split_leave_the_run_unchanged(precision):
     assert digest(8) == ref
     assert digest(48) == ref
     assert digest(16, max_grid=3) == ref
+
+
+def _state_digest(run):
+    # integer currents, fields and every alive particle (as a set, with its
+    # RR residuals) of a run
+    st = run.get_state()
+    keys = ["cell", "off", "ux", "uy", "uz", "w"] + [k for k in ("rx", "ry", "rz") if k in st["sp0"]]
+    h = hashlib.sha256()
+    for k in ("Ex_int", "Ey", "Ez", "By", "Bz", "Jx_int", "Jy_int", "Jz_int"):
+        h.update(np.ascontiguousarray(st[k]).tobytes())
+    for s in (0, 1):
+        p = st[f"sp{s}"]
+        alive = p["cell"] != np.iinfo(np.int32).min
+        ks = [k for k in keys if k in p]
+        q = {k: p[k][alive] for k in ks}
+        order = np.lexsort([q[k] for k in reversed(ks)])
+        for k in ks:
+            h.update(np.ascontiguousarray(q[k][order]).tobytes())
+    return h.hexdigest()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_push_tile_size_leaves_the_run_unchanged(precision):
+    # one state in the laser-foil interaction, stepped alone in the single-run
+    # push's 5,120-particle tiles (four particles' loads in flight) and in a
+    # serving batch's 1,024-particle tiles (two in flight): the tiling decides
+    # only which lanes push which particles, so both end in the same state
+    from paper_1008_1685_amd import Run
+    from paper_1008_1685_amd.serve import Batch
+
+    cfg = preset("c2", ppc=8000, precision=precision)  # 1.6e6 particles per species
+    src = Run(cfg)
+    src.step(3264)  # the pulse reaches the foil near step 3,200
+    st = src.get_state()
+    src.close()
+    parts = {0: st["sp0"], 1: st["sp1"]}
+    fields = {k: st[k] for k in ("Ex", "Ey", "Ez", "By", "Bz", "Ex_int", "Jx_int", "Jy_int", "Jz_int")}
+    steps = 64  # three sorts (every 16 steps)
+
+    alone = Run(cfg)
+    assert alone.get_info()["tile"] == 5120
+    alone.set_state(parts, fields, step=0)
+    start = _state_digest(alone)
+    alone.step(steps)
+    ref = _state_digest(alone)
+    assert ref != start  # the steps move particles and currents
+    assert alone.diag()["gauss_int"] == 0
+    alone.close()
+
+    batch = Batch(precision=precision, max_slots=1, quantum=cfg["sort_interval"],
+                  max_particles=4 * 10 ** 6, max_cells=2 * 10 ** 4)
+    run = Run(cfg, stream=batch.stream)
+    run.set_state(parts, fields, step=0)
+    slot = batch.admit(run, steps)
+    batch.drain()
+    assert batch.poll()[slot] == steps
+    batch.release(slot)
+    assert _state_digest(run) == ref
+    assert run.diag()["gauss_int"] == 0
+    run.close()
+    batch.close()
